@@ -1,0 +1,65 @@
+"""Generator checks: shapes, distinct links per route, distributions, seeds."""
+import numpy as np
+
+from paper_2509_10722_amd import instances as I
+
+
+def _check_pattern(inst):
+    assert inst.row_ptr.dtype == np.int32 and inst.col_idx.dtype == np.int32
+    assert inst.row_ptr[0] == 0 and inst.row_ptr[-1] == inst.col_idx.size
+    assert np.all(np.diff(inst.row_ptr) >= 0)
+    assert inst.col_idx.min() >= 0 and inst.col_idx.max() < inst.n
+    for l in range(inst.m):
+        row = inst.col_idx[inst.row_ptr[l]:inst.row_ptr[l + 1]]
+        assert np.all(np.diff(row) > 0)           # sorted, unique => 0/1
+
+
+def test_tiny_recipe():
+    t = I.tiny()
+    _check_pattern(t)
+    L = np.bincount(t.col_idx, minlength=t.n)
+    assert L.min() >= 2 and L.max() <= 8
+    assert t.m == 200 and t.n == 1000
+    assert np.all((t.c >= 1) & (t.c <= 10))
+    assert (t.utility == I.LOG).sum() == 500
+    assert np.all((t.w[t.utility == I.LOG] >= 0.5) & (t.w[t.utility == I.LOG] <= 2))
+    assert np.all((t.w[t.utility == I.LINEAR] >= 0.1) & (t.w[t.utility == I.LINEAR] <= 1))
+    assert t.lo == 0.0 and t.hi == 10.0
+
+
+def test_seed_reproducible():
+    a, b = I.tiny(), I.tiny()
+    assert np.array_equal(a.col_idx, b.col_idx) and np.array_equal(a.c, b.c)
+    c = I.tiny(seed=7)
+    assert not np.array_equal(a.col_idx, c.col_idx)
+
+
+def test_large_shape_scaled():
+    t = I.large(scale=0.002)
+    _check_pattern(t)
+    L = np.bincount(t.col_idx, minlength=t.n)
+    assert L.min() >= 3 and L.max() <= 40
+    # discrete power law alpha=2.5 on 3..40 has mean 5.83
+    assert abs(L.mean() - 5.83) < 0.2
+    assert np.all(t.utility == I.LOG)
+
+
+def test_transit_routes_are_diagonals():
+    rng = np.random.default_rng(0)
+    t = I.transit_instance(rng, 2000)
+    _check_pattern(t)
+    T = 48
+    rows = np.repeat(np.arange(t.m), np.diff(t.row_ptr))
+    order = np.lexsort((rows, t.col_idx))
+    s, l = t.col_idx[order], rows[order]
+    same = s[1:] == s[:-1]
+    # consecutive links of a trip: next segment, next time bin
+    assert np.all((l[1:] - l[:-1])[same] == T + 1)
+
+
+def test_block_diagonal():
+    a = I.paper_example()
+    b = I.single_link([1.0, 2.0], [0, 0], 3.0)
+    u = I.block_diagonal([a, b])
+    _check_pattern(u)
+    assert u.m == 4 and u.n == 6 and u.nnz == 7
