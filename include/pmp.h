@@ -1,0 +1,183 @@
+/*
+ * pmp.h -- proximal message passing (PMP) for network utility maximization
+ * on AMD Instinct MI355X (gfx950).  C ABI; no exceptions cross it.
+ *
+ * Problem (eq. (2) with the slack form of eq. (3), plus a box on every rate):
+ *
+ *     maximize  sum_j U_j(x_j)   subject to   R x <= c,   lo <= x_j <= hi
+ *
+ *   R  m x n link-route matrix with R_lj = 1 when stream j uses link l
+ *      (eq. (1)); only its pattern is stored (CSR here, CSC built inside).
+ *   U_j = w_j log x_j  (weighted proportional fairness) or  w_j x_j
+ *      (linear), Section II.
+ *
+ * Method: the over-relaxed PMP iteration of Section III-D..G (ADMM on the
+ * terminal graph), held in a compact per-stream / per-link form:
+ *   stream pass  S_j = L_j a_j + sum_{l in route j} v_l;  x_j = prox(S_j)
+ *                (log / linear closed forms of Section III-E, clipped to the
+ *                box); a_j <- alpha x_j + (1 - alpha) a_j
+ *   link pass    y_l = sum_{j on link l} x_j;  ps_l = max(zs_l - u_l, -c_l)
+ *                (slack prox); pbar_l = (y_l + ps_l) / (d_l + 1);
+ *                b_l <- -alpha pbar_l + (1 - alpha) b_l;
+ *                zs_l <- alpha (ps_l - pbar_l) + (1 - alpha) zs_l;
+ *                u_l <- u_l + alpha pbar_l;  v_l = b_l - u_l
+ *   (a_j + b_l is the link-side copy z of terminal (j, l), zs_l that of the
+ *   slack terminal; u is the scaled dual.)  Residuals ||r||, ||s|| and the
+ *   stop rule of Section III-F; residual balancing of rho every
+ *   `adapt_every` iterations with the rescale of u (Section III-G, eqs. (6),
+ *   (7)).  Link prices are lambda = rho u; the slack is s = ps + c.
+ *
+ * Memory: every device buffer lives in one caller-owned workspace (size from
+ * pmp_workspace_size).  The library allocates no device memory itself; it
+ * allocates a small pinned host buffer and a private stream per handle (for
+ * graph capture).  Streams are passed as `void*` holding a hipStream_t
+ * (NULL = the null stream).
+ *
+ * Errors: every call returns a pmp_status.  PMP_ERR_INVALID / PMP_ERR_SHAPE
+ * carry a detail string from pmp_last_error() (thread-local).  Asynchronous
+ * HIP failures surface as PMP_ERR_HIP at the next call that synchronises.
+ * A non-finite residual gives PMP_ERR_NUMERIC.
+ */
+#ifndef PMP_H
+#define PMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMP_OK = 0,
+    PMP_ERR_INVALID = 1,    /* bad problem data or parameters               */
+    PMP_ERR_SHAPE = 2,      /* sizes out of range, workspace too small      */
+    PMP_ERR_NOMEM = 3,      /* host allocation failed                       */
+    PMP_ERR_HIP = 4,        /* a HIP runtime call failed                    */
+    PMP_ERR_NUMERIC = 5,    /* non-finite residual                          */
+    PMP_NOT_CONVERGED = 6,  /* max_iter reached; the result is still valid  */
+    PMP_ERR_STATE = 7       /* call not valid for this handle               */
+} pmp_status;
+
+typedef enum { PMP_UTIL_LOG = 0, PMP_UTIL_LINEAR = 1 } pmp_utility;
+typedef enum { PMP_F32 = 0, PMP_F64 = 1 } pmp_dtype;
+typedef enum { PMP_MEM_HOST = 0, PMP_MEM_DEVICE = 1 } pmp_memory;
+
+/* One NUM instance (eq. (1)-(2)).  All arrays are in `memory`; the floating
+ * point arrays have type `dtype`.
+ *   row_ptr[m+1], col_idx[nnz]  CSR pattern of R: row_ptr[0] = 0,
+ *                               row_ptr[m] = nnz, nondecreasing; col_idx in
+ *                               [0, n), strictly increasing within a row.
+ *   c[m]        capacities, finite and > 0 (Section II).
+ *   w[n]        weights, finite and > 0 (Section III-B).
+ *   utility[n]  pmp_utility per stream.
+ *   lo, hi      box, 0 <= lo < hi; hi may be +inf unless some stream has an
+ *               empty route (such a stream takes x = hi).
+ * HOST arrays are copied into the workspace during pmp_setup; DEVICE arrays
+ * are read during pmp_setup only (c, w and the pattern are copied too), so
+ * they may be freed after it returns.  m >= 1, n >= 0 and nnz < 2^31. */
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const void *c;
+    const void *w;
+    const uint8_t *utility;
+    double lo, hi;
+    pmp_dtype dtype;
+    pmp_memory memory;
+} pmp_problem;
+
+/* Solver controls (Section III-F, III-G).
+ *   rho0         initial penalty (> 0)
+ *   alpha        over-relaxation in [1, 2) (the paper uses 1.6)
+ *   mu, gamma    residual-balancing thresholds (> 1; the paper uses 2, 1.1)
+ *   eps_abs      absolute tolerance; stop when ||r||, ||s|| < eps_abs sqrt(J),
+ *                J = nnz + m terminals
+ *   adapt_every  rho balancing period in iterations (0 = fixed rho); must be
+ *                a multiple of check_every
+ *   check_every  residual / stop-test period of pmp_solve (>= 1)
+ *   max_iter     iteration cap of one pmp_solve call */
+typedef struct {
+    double rho0, alpha, mu, gamma, eps_abs;
+    int32_t adapt_every, check_every, max_iter;
+} pmp_params;
+
+typedef struct {
+    int64_t iterations;   /* iterations done by this pmp_solve call       */
+    double r_norm;        /* ||r||_2 at the last check                     */
+    double s_norm;        /* ||s||_2 at the last check                     */
+    double eps_tol;       /* eps_abs sqrt(J)                               */
+    double rho;           /* current penalty                               */
+    pmp_status status;    /* PMP_OK (converged) or PMP_NOT_CONVERGED, ...  */
+} pmp_result;
+
+typedef struct pmp_handle pmp_handle;
+
+/* Defaults: rho0 1, alpha 1.6, mu 2, gamma 1.1, eps_abs 1e-4, adapt_every 50,
+ * check_every 10, max_iter 100000 (Section III-G's constants). */
+pmp_status pmp_params_default(pmp_params *params);
+
+/* Workspace bytes needed for `problem` (reads only m, n, nnz, dtype). */
+pmp_status pmp_workspace_size(const pmp_problem *problem, const pmp_params *params,
+                              size_t *bytes);
+
+/* Validate the problem, copy it into `workspace` (device memory, >= the size
+ * above, 256-byte aligned), build the CSC pattern and the block tables on the
+ * device and zero the state (a = b = zs = u = 0, rho = rho0: the all-zero
+ * start of the ADMM iteration).  Work is queued on `stream` and the call
+ * synchronises it before returning.  On success *out owns host resources
+ * until pmp_destroy. */
+pmp_status pmp_setup(const pmp_problem *problem, const pmp_params *params,
+                     void *workspace, size_t workspace_bytes, void *stream,
+                     pmp_handle **out);
+
+/* Queue k iterations on the handle's stream (asynchronous).  rho balancing
+ * runs at multiples of adapt_every; no stop test.  The last iteration also
+ * computes ||r|| and ||s||, read by pmp_residuals. */
+pmp_status pmp_iterate(pmp_handle *h, int32_t k);
+
+/* Synchronise and return the residuals of the last check and the iteration
+ * count. Any pointer may be NULL. */
+pmp_status pmp_residuals(pmp_handle *h, double *r_norm, double *s_norm,
+                         int64_t *iteration);
+
+/* Iterate until ||r||, ||s|| < eps_tol at a check iteration (iteration
+ * counts that are multiples of check_every) or for max_iter iterations.  Replays a captured hipGraph
+ * of check_every iterations; the stop decision and rho balancing stay on the
+ * device.  Returns PMP_OK on convergence, PMP_NOT_CONVERGED at max_iter. */
+pmp_status pmp_solve(pmp_handle *h, pmp_result *out);
+
+/* Copy the current solution into device buffers of the problem's dtype:
+ * x[n] rates, lambda[m] link prices rho u, slack[m] = ps + c.  Any pointer
+ * may be NULL.  Queued on the handle's stream; synchronises before return. */
+pmp_status pmp_get_solution(pmp_handle *h, void *x, void *lambda, void *slack);
+
+/* Iterate state for warm starts (Section V-D re-solves): a[n], b[m], zs[m],
+ * u[m] in the problem's dtype, packed in that order, followed by rho
+ * (double) and the iteration count (int64).  Size from pmp_state_size.
+ * `state` is device memory. */
+pmp_status pmp_state_size(pmp_handle *h, size_t *bytes);
+pmp_status pmp_get_state(pmp_handle *h, void *state);
+pmp_status pmp_set_state(pmp_handle *h, const void *state);
+
+/* Replace the capacities c[m] (device memory, problem dtype, > 0) keeping the
+ * iterate: the warm-started re-solve after degradation of Section V-D. */
+pmp_status pmp_update_capacity(pmp_handle *h, const void *c_new);
+
+/* Device pointers to the internal rate and price-related vectors (x[n] and
+ * u[m]) for zero-copy inspection; valid until pmp_destroy. */
+pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **b,
+                            void **zs, void **v);
+
+pmp_status pmp_destroy(pmp_handle *h);
+
+const char *pmp_status_string(pmp_status s);
+const char *pmp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMP_H */

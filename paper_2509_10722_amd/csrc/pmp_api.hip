@@ -1,0 +1,631 @@
+// C ABI of the PMP library (include/pmp.h): validation, workspace layout,
+// setup, the asynchronous iteration queue, the graph-replayed solve loop,
+// solution / state access.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pmp_internal.h"
+
+using namespace pmp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pmp_status fail(pmp_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(PMP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kSlots = 4;   // pipelined chunks in flight in pmp_solve
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
+    size_t sblk, lblk, spart, lpart, ctl, hist, util, total;
+    int nsb_max, nlb_max;
+};
+
+Layout plan(int m, int n, long long nnz, size_t sz)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    // Greedy blocks: each has kBlock segments or is closed by kCap, so two
+    // consecutive blocks hold more than kCap nonzeros.
+    L.nsb_max = (int)std::min<long long>((long long)n, n / kBlock + 2 * nnz / kCap + 2);
+    L.nlb_max = (int)std::min<long long>((long long)m, m / kBlock + 2 * nnz / kCap + 2);
+    L.row_ptr = take(((size_t)m + 1) * 4);
+    L.col_idx = take((size_t)nnz * 4);
+    L.col_ptr = take(((size_t)n + 1) * 4);
+    L.row_idx = take((size_t)nnz * 4);
+    L.c = take((size_t)m * sz);
+    L.wsig = take((size_t)n * sz);
+    // a and x are contiguous: the transpose scratch (n + n/2048 + 1 ints)
+    // lives there during setup.
+    L.a = take(std::max((size_t)n * sz, transpose_scratch_ints(n) * 4));
+    L.x = take((size_t)n * sz);
+    L.b = take((size_t)m * sz);
+    L.zs = take((size_t)m * sz);
+    L.u = take((size_t)m * sz);
+    L.v = take((size_t)m * sz);
+    L.y_prev = take((size_t)m * 8);
+    L.ps_prev = take((size_t)m * 8);
+    L.sblk = take(((size_t)L.nsb_max + 1) * 4);
+    L.lblk = take(((size_t)L.nlb_max + 1) * 4);
+    L.spart = take((size_t)L.nsb_max * 8);
+    L.lpart = take((size_t)L.nlb_max * 16);
+    L.ctl = take(sizeof(Ctl));
+    L.hist = take(sizeof(HistEntry) * kHist);
+    L.util = take((size_t)n);
+    L.total = off;
+    return L;
+}
+
+std::vector<int> make_blocks(const std::vector<int> &ptr, int count)
+{
+    std::vector<int> blk;
+    blk.reserve(count / 64 + 2);
+    blk.push_back(0);
+    int s = 0;
+    while (s < count) {
+        int e = s;
+        long long cnt = 0;
+        while (e < count && e - s < kBlock && cnt + (ptr[e + 1] - ptr[e]) <= kCap) {
+            cnt += ptr[e + 1] - ptr[e];
+            ++e;
+        }
+        if (e == s) e = s + 1;   // a segment longer than kCap on its own
+        blk.push_back(e);
+        s = e;
+    }
+    return blk;
+}
+
+std::string flag_text(unsigned f)
+{
+    std::string s;
+    if (f & kErrRowPtr) s += "row_ptr must start at 0, end at nnz and be nondecreasing; ";
+    if (f & kErrColRange) s += "col_idx out of range [0, n); ";
+    if (f & kErrColOrder)
+        s += "col_idx not strictly increasing within a row (duplicate link on a route "
+             "would make R non-0/1); ";
+    if (f & kErrCap) s += "capacities must be finite and > 0; ";
+    if (f & kErrWeight) s += "weights must be finite and > 0; ";
+    if (f & kErrUtility) s += "utility must be 0 (log) or 1 (linear); ";
+    if (f & kErrEmptyRoute) s += "a stream with an empty route needs a finite hi; ";
+    return s;
+}
+
+}  // namespace
+
+struct pmp_handle {
+    int m = 0, n = 0;
+    long long nnz = 0;
+    pmp_dtype dtype = PMP_F32;
+    pmp_params prm{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Dev<float> df{};
+    Dev<double> dd{};
+    Ctl *ctl = nullptr;            // device
+    Ctl *ctl_host = nullptr;       // pinned, kSlots entries
+    hipEvent_t ev[kSlots] = {};
+    long long iter_enq = 0;        // iterations queued
+    long long iter_fin = 0;        // iteration of the last queued check
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+template <typename T>
+Dev<T> &dev_of(pmp_handle *h);
+template <>
+Dev<float> &dev_of<float>(pmp_handle *h) { return h->df; }
+template <>
+Dev<double> &dev_of<double>(pmp_handle *h) { return h->dd; }
+
+pmp_status check_params(const pmp_params *p)
+{
+    if (!p) return fail(PMP_ERR_INVALID, "params is NULL");
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(PMP_ERR_INVALID, "rho0 must be > 0");
+    if (!(p->alpha > 0.0 && p->alpha < 2.0)) return fail(PMP_ERR_INVALID, "alpha must be in (0, 2)");
+    if (!(p->mu > 1.0) || !(p->gamma > 1.0)) return fail(PMP_ERR_INVALID, "mu and gamma must be > 1");
+    if (!(p->eps_abs >= 0.0)) return fail(PMP_ERR_INVALID, "eps_abs must be >= 0");
+    if (p->check_every < 1) return fail(PMP_ERR_INVALID, "check_every must be >= 1");
+    if (p->adapt_every < 0 || (p->adapt_every > 0 && p->adapt_every % p->check_every != 0))
+        return fail(PMP_ERR_INVALID, "adapt_every must be 0 or a multiple of check_every");
+    if (p->max_iter < 0) return fail(PMP_ERR_INVALID, "max_iter must be >= 0");
+    return PMP_OK;
+}
+
+pmp_status check_shape(const pmp_problem *p)
+{
+    if (!p) return fail(PMP_ERR_INVALID, "problem is NULL");
+    if (p->m < 1 || p->n < 0) return fail(PMP_ERR_SHAPE, "m >= 1 and n >= 0 required");
+    if (p->nnz < 0 || p->nnz >= (1LL << 31)) return fail(PMP_ERR_SHAPE, "nnz must be in [0, 2^31)");
+    if (p->dtype != PMP_F32 && p->dtype != PMP_F64) return fail(PMP_ERR_INVALID, "unknown dtype");
+    if (p->memory != PMP_MEM_HOST && p->memory != PMP_MEM_DEVICE)
+        return fail(PMP_ERR_INVALID, "unknown memory kind");
+    if (!(p->lo >= 0.0) || !std::isfinite(p->lo) || !(p->hi > p->lo) || std::isnan(p->hi))
+        return fail(PMP_ERR_INVALID, "box must satisfy 0 <= lo < hi (lo finite)");
+    if ((p->m > 0 && !p->row_ptr) || (p->nnz > 0 && !p->col_idx) || (p->m > 0 && !p->c) ||
+        (p->n > 0 && (!p->w || !p->utility)))
+        return fail(PMP_ERR_INVALID, "problem arrays must not be NULL");
+    return PMP_OK;
+}
+
+template <typename T>
+pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
+{
+    const int m = p->m, n = p->n;
+    const long long nnz = p->nnz;
+    const Layout L = plan(m, n, nnz, sizeof(T));
+    hipStream_t s = h->stream;
+    Dev<T> &d = dev_of<T>(h);
+    d.m = m;
+    d.n = n;
+    d.nnz = nnz;
+    int *row_ptr = (int *)(ws + L.row_ptr);
+    int *col_idx = (int *)(ws + L.col_idx);
+    int *col_ptr = (int *)(ws + L.col_ptr);
+    int *row_idx = (int *)(ws + L.row_idx);
+    d.row_ptr = row_ptr;
+    d.col_idx = col_idx;
+    d.col_ptr = col_ptr;
+    d.row_idx = row_idx;
+    d.c = (T *)(ws + L.c);
+    d.wsig = (T *)(ws + L.wsig);
+    d.a = (T *)(ws + L.a);
+    d.x = (T *)(ws + L.x);
+    d.b = (T *)(ws + L.b);
+    d.zs = (T *)(ws + L.zs);
+    d.u = (T *)(ws + L.u);
+    d.v = (T *)(ws + L.v);
+    d.y_prev = (double *)(ws + L.y_prev);
+    d.ps_prev = (double *)(ws + L.ps_prev);
+    d.sblk = (int *)(ws + L.sblk);
+    d.lblk = (int *)(ws + L.lblk);
+    d.spart = (double *)(ws + L.spart);
+    d.lpart = (double *)(ws + L.lpart);
+    d.ctl = (Ctl *)(ws + L.ctl);
+    d.hist = (HistEntry *)(ws + L.hist);
+    d.lo = p->lo;
+    d.hi = p->hi;
+    d.alpha = h->prm.alpha;
+    h->ctl = d.ctl;
+
+    const double J = (double)nnz + (double)m;
+    launch_ctl_init(d.ctl, h->prm.rho0, h->prm.eps_abs * std::sqrt(J), h->prm.mu, h->prm.gamma,
+                    h->prm.adapt_every, s);
+
+    // Inputs into the workspace.
+    const hipMemcpyKind kind =
+        p->memory == PMP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(row_ptr, p->row_ptr, ((size_t)m + 1) * 4, kind, s));
+    if (nnz) HIP_TRY(hipMemcpyAsync(col_idx, p->col_idx, (size_t)nnz * 4, kind, s));
+    const T *c_src = (const T *)p->c;
+    const T *w_src = (const T *)p->w;
+    const uint8_t *u_src = p->utility;
+    if (p->memory == PMP_MEM_HOST) {
+        if (m) HIP_TRY(hipMemcpyAsync((void *)d.c, p->c, (size_t)m * sizeof(T), kind, s));
+        if (n) HIP_TRY(hipMemcpyAsync((void *)d.wsig, p->w, (size_t)n * sizeof(T), kind, s));
+        if (n) HIP_TRY(hipMemcpyAsync(ws + L.util, p->utility, (size_t)n, kind, s));
+        c_src = d.c;
+        w_src = d.wsig;
+        u_src = (const uint8_t *)(ws + L.util);
+    }
+    launch_validate_csr(row_ptr, col_idx, m, n, nnz, d.ctl, s);
+    launch_check_vectors<T>(c_src, w_src, u_src, m, n, d.ctl, s);
+    HIP_TRY(hipGetLastError());
+    Ctl hc;
+    HIP_TRY(hipMemcpyAsync(&hc, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc.flags) return fail(PMP_ERR_INVALID, "invalid problem: %s", flag_text(hc.flags).c_str());
+
+    // CSC pattern (setup step of the stream pass).
+    launch_transpose(row_ptr, col_idx, m, n, nnz, col_ptr, row_idx, (int *)(ws + L.a), s);
+    launch_check_routes(col_ptr, n, p->hi, d.ctl, s);
+    launch_init_state<T>(d, c_src, w_src, u_src, s);
+    HIP_TRY(hipGetLastError());
+
+    // Workgroup tables from the two pointer arrays.
+    std::vector<int> hrow((size_t)m + 1), hcol((size_t)n + 1);
+    HIP_TRY(hipMemcpyAsync(hrow.data(), row_ptr, hrow.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hcol.data(), col_ptr, hcol.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hc, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc.flags) return fail(PMP_ERR_INVALID, "invalid problem: %s", flag_text(hc.flags).c_str());
+    std::vector<int> sblk = make_blocks(hcol, n), lblk = make_blocks(hrow, m);
+    d.nsb = (int)sblk.size() - 1;
+    d.nlb = (int)lblk.size() - 1;
+    if (d.nsb > L.nsb_max || d.nlb > L.nlb_max)
+        return fail(PMP_ERR_SHAPE, "internal: block tables exceed their bound");
+    HIP_TRY(hipMemcpyAsync((void *)d.sblk, sblk.data(), sblk.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((void *)d.lblk, lblk.data(), lblk.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+// Queue iterations [h->iter_enq + 1, h->iter_enq + k] without a stop test;
+// residuals at the last one and at every balancing iteration.
+template <typename T>
+void enqueue_iterations(pmp_handle *h, int k, hipStream_t s)
+{
+    Dev<T> &d = dev_of<T>(h);
+    const int adapt = h->prm.adapt_every;
+    for (int i = 1; i <= k; ++i) {
+        const long long it = h->iter_enq + 1;
+        const bool check = i == k || (adapt > 0 && it % adapt == 0);
+        const bool next_check = i < k && (i + 1 == k || (adapt > 0 && (it + 1) % adapt == 0));
+        launch_stream_pass<T>(d, check, s);
+        const int mode = check ? kCheck : (next_check ? kSave : kPlain);
+        launch_link_pass<T>(d, mode, it - h->iter_fin, 0, s);
+        if (check) {
+            h->iter_fin = it;
+            if (adapt > 0 && it % adapt == 0) launch_rescale<T>(d, s);
+        }
+        h->iter_enq = it;
+    }
+}
+
+// One graph = check_every iterations ending in a check with the stop test.
+template <typename T>
+pmp_status build_graph(pmp_handle *h)
+{
+    Dev<T> &d = dev_of<T>(h);
+    const int ce = h->prm.check_every;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 1; i <= ce; ++i) {
+        const bool check = i == ce;
+        launch_stream_pass<T>(d, check, h->cap_stream);
+        const int mode = check ? kCheck : (i == ce - 1 ? kSave : kPlain);
+        launch_link_pass<T>(d, mode, ce, 1, h->cap_stream);
+    }
+    launch_rescale<T>(d, h->cap_stream);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(h->cap_stream, &g));
+    h->graph = g;
+    HIP_TRY(hipGraphInstantiateWithFlags(&h->graph_exec, g, 0));
+    return PMP_OK;
+}
+
+template <typename T>
+pmp_status solve_impl(pmp_handle *h, pmp_result *out)
+{
+    hipStream_t s = h->stream;
+    const int ce = h->prm.check_every;
+    const long long start = h->iter_enq;
+    long long budget = h->prm.max_iter;
+    launch_ctl_clear_done(h->ctl, s);
+    // Align chunks so that every check lands on a multiple of check_every.
+    long long align = (ce - h->iter_enq % ce) % ce;
+    if (align > budget) align = budget;
+    if (align > 0) {
+        enqueue_iterations<T>(h, (int)align, s);
+        budget -= align;
+    }
+    HIP_TRY(hipGetLastError());
+    if (!h->graph_exec) {
+        pmp_status st = build_graph<T>(h);
+        if (st != PMP_OK) return st;
+    }
+    const long long chunks = budget / ce;
+    const long long leftover = budget % ce;
+    bool done = false;
+    long long launched = 0, waited = 0;
+    while (!done && waited < chunks) {
+        while (launched < chunks && launched - waited < kSlots) {
+            HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+            const int slot = (int)(launched % kSlots);
+            HIP_TRY(hipMemcpyAsync(&h->ctl_host[slot], h->ctl, sizeof(Ctl),
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(h->ev[slot], s));
+            ++launched;
+        }
+        const int slot = (int)(waited % kSlots);
+        HIP_TRY(hipEventSynchronize(h->ev[slot]));
+        ++waited;
+        if (h->ctl_host[slot].done) done = true;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    Ctl c;
+    HIP_TRY(hipMemcpy(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    h->iter_enq = h->iter_fin = c.iter;
+    if (!c.done && leftover > 0) {
+        enqueue_iterations<T>(h, (int)leftover, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpy(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    }
+    pmp_status st = c.done ? (pmp_status)c.status : PMP_NOT_CONVERGED;
+    if (out) {
+        out->iterations = c.iter - start;
+        out->r_norm = c.r_norm;
+        out->s_norm = c.s_norm;
+        out->eps_tol = c.eps_tol;
+        out->rho = c.rho;
+        out->status = st;
+    }
+    if (st == PMP_ERR_NUMERIC) return fail(st, "non-finite residual at iteration %lld", c.iter);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+pmp_status pmp_params_default(pmp_params *p)
+{
+    if (!p) return fail(PMP_ERR_INVALID, "params is NULL");
+    p->rho0 = 1.0;
+    p->alpha = 1.6;
+    p->mu = 2.0;
+    p->gamma = 1.1;
+    p->eps_abs = 1e-4;
+    p->adapt_every = 50;
+    p->check_every = 10;
+    p->max_iter = 100000;
+    return PMP_OK;
+}
+
+pmp_status pmp_workspace_size(const pmp_problem *problem, const pmp_params *params,
+                              size_t *bytes)
+{
+    (void)params;
+    if (!problem || !bytes) return fail(PMP_ERR_INVALID, "NULL argument");
+    if (problem->m < 0 || problem->n < 0 || problem->nnz < 0 || problem->nnz >= (1LL << 31))
+        return fail(PMP_ERR_SHAPE, "m, n >= 0 and 0 <= nnz < 2^31 required");
+    const size_t sz = problem->dtype == PMP_F64 ? 8 : 4;
+    *bytes = plan(problem->m, problem->n, problem->nnz, sz).total;
+    return PMP_OK;
+}
+
+pmp_status pmp_setup(const pmp_problem *problem, const pmp_params *params, void *workspace,
+                     size_t workspace_bytes, void *stream, pmp_handle **out)
+{
+    if (!out) return fail(PMP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    pmp_status st = check_shape(problem);
+    if (st != PMP_OK) return st;
+    st = check_params(params);
+    if (st != PMP_OK) return st;
+    const size_t sz = problem->dtype == PMP_F64 ? 8 : 4;
+    const Layout L = plan(problem->m, problem->n, problem->nnz, sz);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(PMP_ERR_SHAPE, "workspace of %zu bytes needed, %zu given", L.total,
+                    workspace_bytes);
+    if ((uintptr_t)workspace % kAlign)
+        return fail(PMP_ERR_INVALID, "workspace must be 256-byte aligned");
+    pmp_handle *h = new (std::nothrow) pmp_handle();
+    if (!h) return fail(PMP_ERR_NOMEM, "handle allocation failed");
+    h->m = problem->m;
+    h->n = problem->n;
+    h->nnz = problem->nnz;
+    h->dtype = problem->dtype;
+    h->prm = *params;
+    h->stream = (hipStream_t)stream;
+    auto cleanup = [&](pmp_status s2) {
+        pmp_destroy(h);
+        return s2;
+    };
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(PMP_ERR_HIP, "hipStreamCreateWithFlags failed"));
+    if (hipHostMalloc((void **)&h->ctl_host, sizeof(Ctl) * kSlots, hipHostMallocDefault) !=
+        hipSuccess)
+        return cleanup(fail(PMP_ERR_HIP, "hipHostMalloc failed"));
+    for (auto &e : h->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(PMP_ERR_HIP, "hipEventCreate failed"));
+    st = problem->dtype == PMP_F32 ? setup_impl<float>(h, problem, (char *)workspace)
+                                   : setup_impl<double>(h, problem, (char *)workspace);
+    if (st != PMP_OK) return cleanup(st);
+    *out = h;
+    return PMP_OK;
+}
+
+pmp_status pmp_iterate(pmp_handle *h, int32_t k)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    if (k < 0) return fail(PMP_ERR_INVALID, "k must be >= 0");
+    if (k == 0) return PMP_OK;
+    launch_ctl_clear_done(h->ctl, h->stream);
+    if (h->dtype == PMP_F32) enqueue_iterations<float>(h, k, h->stream);
+    else enqueue_iterations<double>(h, k, h->stream);
+    HIP_TRY(hipGetLastError());
+    return PMP_OK;
+}
+
+pmp_status pmp_residuals(pmp_handle *h, double *r_norm, double *s_norm, int64_t *iteration)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (r_norm) *r_norm = c.r_norm;
+    if (s_norm) *s_norm = c.s_norm;
+    if (iteration) *iteration = c.iter;
+    if (c.status == PMP_ERR_NUMERIC)
+        return fail(PMP_ERR_NUMERIC, "non-finite residual at iteration %lld", c.iter);
+    return PMP_OK;
+}
+
+pmp_status pmp_solve(pmp_handle *h, pmp_result *out)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    return h->dtype == PMP_F32 ? solve_impl<float>(h, out) : solve_impl<double>(h, out);
+}
+
+pmp_status pmp_get_solution(pmp_handle *h, void *x, void *lambda, void *slack)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    if (h->dtype == PMP_F32)
+        launch_solution<float>(h->df, (float *)x, (float *)lambda, (float *)slack, h->stream);
+    else
+        launch_solution<double>(h->dd, (double *)x, (double *)lambda, (double *)slack, h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PMP_OK;
+}
+
+pmp_status pmp_state_size(pmp_handle *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(PMP_ERR_INVALID, "NULL argument");
+    const size_t sz = h->dtype == PMP_F64 ? 8 : 4;
+    *bytes = ((size_t)h->n + 3 * (size_t)h->m) * sz + 16;
+    return PMP_OK;
+}
+
+pmp_status pmp_get_state(pmp_handle *h, void *state)
+{
+    if (!h || !state) return fail(PMP_ERR_INVALID, "NULL argument");
+    const size_t sz = h->dtype == PMP_F64 ? 8 : 4;
+    char *p = (char *)state;
+    void *a, *b, *zs, *u;
+    if (h->dtype == PMP_F32) { a = h->df.a; b = h->df.b; zs = h->df.zs; u = h->df.u; }
+    else { a = h->dd.a; b = h->dd.b; zs = h->dd.zs; u = h->dd.u; }
+    hipStream_t s = h->stream;
+    const size_t n = (size_t)h->n * sz, m = (size_t)h->m * sz;
+    if (n) HIP_TRY(hipMemcpyAsync(p, a, n, hipMemcpyDeviceToDevice, s));
+    if (m) {
+        HIP_TRY(hipMemcpyAsync(p + n, b, m, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(p + n + m, zs, m, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(p + n + 2 * m, u, m, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipMemcpyAsync(p + n + 3 * m, &h->ctl->rho, 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(p + n + 3 * m + 8, &h->ctl->iter, 8, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+pmp_status pmp_set_state(pmp_handle *h, const void *state)
+{
+    if (!h || !state) return fail(PMP_ERR_INVALID, "NULL argument");
+    const size_t sz = h->dtype == PMP_F64 ? 8 : 4;
+    const char *p = (const char *)state;
+    void *a, *b, *zs, *u;
+    if (h->dtype == PMP_F32) { a = h->df.a; b = h->df.b; zs = h->df.zs; u = h->df.u; }
+    else { a = h->dd.a; b = h->dd.b; zs = h->dd.zs; u = h->dd.u; }
+    hipStream_t s = h->stream;
+    const size_t n = (size_t)h->n * sz, m = (size_t)h->m * sz;
+    if (n) HIP_TRY(hipMemcpyAsync(a, p, n, hipMemcpyDeviceToDevice, s));
+    if (m) {
+        HIP_TRY(hipMemcpyAsync(b, p + n, m, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(zs, p + n + m, m, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(u, p + n + 2 * m, m, hipMemcpyDeviceToDevice, s));
+    }
+    double rho;
+    long long it;
+    HIP_TRY(hipMemcpyAsync(&rho, p + n + 3 * m, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&it, p + n + 3 * m + 8, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!(rho > 0.0) || !std::isfinite(rho)) return fail(PMP_ERR_INVALID, "state rho must be > 0");
+    if (it < 0) return fail(PMP_ERR_INVALID, "state iteration must be >= 0");
+    // Re-seed the control block (keeping the tolerances) and v = b - u.
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    launch_ctl_init(h->ctl, rho, c.eps_tol, c.mu, c.gamma, c.adapt_every, s);
+    HIP_TRY(hipMemcpyAsync(&h->ctl->iter, &it, 8, hipMemcpyHostToDevice, s));
+    if (h->dtype == PMP_F32) launch_refresh_v<float>(h->df, s);
+    else launch_refresh_v<double>(h->dd, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    h->iter_enq = h->iter_fin = it;
+    return PMP_OK;
+}
+
+pmp_status pmp_update_capacity(pmp_handle *h, const void *c_new)
+{
+    if (!h || !c_new) return fail(PMP_ERR_INVALID, "NULL argument");
+    if (h->dtype == PMP_F32) launch_copy_capacity<float>(h->df, (const float *)c_new, h->stream);
+    else launch_copy_capacity<double>(h->dd, (const double *)c_new, h->stream);
+    HIP_TRY(hipGetLastError());
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (c.flags & kErrCap) return fail(PMP_ERR_INVALID, "capacities must be finite and > 0");
+    return PMP_OK;
+}
+
+pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **b, void **zs,
+                            void **v)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    if (h->dtype == PMP_F32) {
+        if (x) *x = h->df.x;
+        if (u) *u = h->df.u;
+        if (a) *a = h->df.a;
+        if (b) *b = h->df.b;
+        if (zs) *zs = h->df.zs;
+        if (v) *v = h->df.v;
+    } else {
+        if (x) *x = h->dd.x;
+        if (u) *u = h->dd.u;
+        if (a) *a = h->dd.a;
+        if (b) *b = h->dd.b;
+        if (zs) *zs = h->dd.zs;
+        if (v) *v = h->dd.v;
+    }
+    return PMP_OK;
+}
+
+pmp_status pmp_destroy(pmp_handle *h)
+{
+    if (!h) return PMP_OK;
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+    return PMP_OK;
+}
+
+const char *pmp_status_string(pmp_status s)
+{
+    switch (s) {
+    case PMP_OK: return "ok";
+    case PMP_ERR_INVALID: return "invalid argument";
+    case PMP_ERR_SHAPE: return "shape or size error";
+    case PMP_ERR_NOMEM: return "out of host memory";
+    case PMP_ERR_HIP: return "HIP runtime error";
+    case PMP_ERR_NUMERIC: return "non-finite residual";
+    case PMP_NOT_CONVERGED: return "not converged";
+    case PMP_ERR_STATE: return "invalid handle state";
+    }
+    return "unknown status";
+}
+
+const char *pmp_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal definitions shared by the PMP host layer and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pmp.h"
+
+namespace pmp {
+
+// Workgroup shape of the stream and link passes: one wave64 x 4.
+constexpr int kBlock = 256;
+// Entries of R staged in LDS per workgroup (index stream + gathered values).
+// A workgroup covers at most kBlock streams (links) and at most kCap
+// nonzeros, or a single longer column (row) on its own.
+constexpr int kCap = 4096;
+// Device history ring of (iteration, ||r||, ||s||, rho), one entry per check.
+constexpr int kHist = 4096;
+
+// Device-resident control block.  Kernels read rho and the done flag from
+// here, so a captured graph stays valid while rho changes (Section III-G
+// balancing happens on the device).
+struct Ctl {
+    double rho;            // penalty of the next iteration
+    double ratio;          // pending u rescale rho_old / rho_new (1 = none)
+    double r_norm;         // ||r|| at the last check
+    double s_norm;         // ||s|| at the last check
+    double eps_tol;        // eps_abs sqrt(J)
+    double mu, gamma;      // balancing thresholds
+    long long iter;        // iterations completed at the last check
+    long long nhist;       // checks recorded in the history ring
+    int adapt_every;       // 0 = fixed rho
+    int done;              // 1: stop rule met or numeric failure
+    int status;            // pmp_status of the last check
+    unsigned int arrive;   // arrival counter of the last-workgroup finalize
+    unsigned int flags;    // setup validation error bits
+    int pad;
+};
+
+struct HistEntry {
+    long long iter;
+    double r_norm, s_norm, rho;
+};
+
+// Setup validation error bits.
+enum : unsigned {
+    kErrRowPtr = 1u << 0,
+    kErrColRange = 1u << 1,
+    kErrColOrder = 1u << 2,
+    kErrCap = 1u << 3,
+    kErrWeight = 1u << 4,
+    kErrUtility = 1u << 5,
+    kErrEmptyRoute = 1u << 6,
+};
+
+// Link-pass flavours: PLAIN does the PMP update only; SAVE also keeps y and
+// ps for the next iteration's residual; CHECK forms the residual partials
+// against the saved values, keeps the new ones, and the last workgroup to
+// finish reduces the partials and takes the stop / rho decisions.
+enum LinkMode : int { kPlain = 0, kSave = 1, kCheck = 2 };
+
+// Device pointers of one instance (all inside the caller's workspace).
+template <typename T>
+struct Dev {
+    int m, n;
+    long long nnz;
+    const int *row_ptr, *col_idx;   // CSR
+    const int *col_ptr, *row_idx;   // CSC
+    const T *c;                     // [m]
+    const T *wsig;                  // [n] w for log streams, -w for linear
+    T *a, *x;                       // [n]
+    T *b, *zs, *u, *v;              // [m]
+    double *y_prev, *ps_prev;       // [m] saved link sums / slack prox
+    const int *sblk;                // [nsb+1] stream workgroup boundaries
+    const int *lblk;                // [nlb+1] link workgroup boundaries
+    int nsb, nlb;
+    double *spart;                  // [nsb]   stream residual partials
+    double *lpart;                  // [2 nlb] link residual partials
+    double lo, hi, alpha;
+    Ctl *ctl;
+    HistEntry *hist;
+};
+
+// Launchers (pmp_kernels.hip).
+template <typename T>
+void launch_stream_pass(const Dev<T> &d, bool check, hipStream_t s);
+template <typename T>
+void launch_link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t s);
+template <typename T>
+void launch_rescale(const Dev<T> &d, hipStream_t s);
+template <typename T>
+void launch_refresh_v(const Dev<T> &d, hipStream_t s);
+template <typename T>
+void launch_init_state(const Dev<T> &d, const T *c_in, const T *w_in, const uint8_t *util,
+                       hipStream_t s);
+template <typename T>
+void launch_check_vectors(const T *c, const T *w, const uint8_t *util, int m, int n,
+                          Ctl *ctl, hipStream_t s);
+template <typename T>
+void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s);
+template <typename T>
+void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s);
+
+void launch_validate_csr(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
+                         Ctl *ctl, hipStream_t s);
+// CSR -> CSC transpose of the pattern; `tmp` holds n + 1 + scan scratch ints.
+size_t transpose_scratch_ints(int n);
+void launch_transpose(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
+                      int *col_ptr, int *row_idx, int *tmp, hipStream_t s);
+void launch_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gamma,
+                     int adapt_every, hipStream_t s);
+void launch_ctl_clear_done(Ctl *ctl, hipStream_t s);
+void launch_fill_int(int *p, int value, size_t count, hipStream_t s);
+
+}  // namespace pmp

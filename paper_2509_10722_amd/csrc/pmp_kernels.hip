@@ -1,0 +1,692 @@
+// HIP kernels of the PMP iteration for gfx950 (CDNA4, wave64).
+//
+// The two passes of one iteration are segmented gather-sums over the 0/1
+// pattern of R with the per-stream / per-link PMP algebra fused into their
+// epilogues:
+//   stream pass  CSC gather of v  -> S_j -> prox (Section III-E) -> x_j, a_j
+//   link pass    CSR gather of x  -> y_l -> slack prox, link average,
+//                over-relaxed z / u updates (Section III-G) -> b, zs, u, v
+// Workgroups own consecutive segments (<= 256 segments, <= kCap nonzeros):
+// all 256 lanes stream the workgroup's index range with coalesced,
+// non-temporal loads and issue the gathers together, the gathered values are
+// staged in LDS, and then one lane per segment sums its run in FP64 in a
+// fixed order (no atomics; results are bitwise reproducible).  A segment
+// longer than kCap gets a workgroup of its own that strides over it.
+#include "pmp_internal.h"
+
+#include <cmath>
+
+namespace pmp {
+
+namespace {
+
+__device__ __forceinline__ int ld_stream(const int *p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup in a fixed order; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) r += sh[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Stage tab[idx[i]] for i < cnt into LDS.  Every lane first loads its share of
+// the index stream, then issues all of its gathers, then writes LDS, so up to
+// kCap / kBlock gathers per lane are in flight together.
+template <typename T>
+__device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
+                                             const T *__restrict__ tab, T *sh, int cnt)
+{
+    constexpr int R = kCap / kBlock;
+    int id[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kBlock + threadIdx.x;
+        id[r] = i < cnt ? ld_stream(idx + i) : -1;
+    }
+    T val[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) val[r] = id[r] >= 0 ? tab[id[r]] : T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kBlock + threadIdx.x;
+        if (i < cnt) sh[i] = val[r];
+    }
+}
+
+// Proximal operator of one traffic stream with L terminals and sum of
+// arguments S (Section III-E), clipped to the box.  wsig > 0: log utility
+// with weight wsig; wsig < 0: linear utility with weight -wsig.  For S < 0 the
+// log root uses the equal form 2w / (rho (sqrt(S^2 + 4wL/rho) - S)).
+__device__ __forceinline__ double prox_stream(double S, int L, double wsig, double rho,
+                                              double lo, double hi)
+{
+    if (L == 0) return hi;
+    double x;
+    const double dl = (double)L;
+    if (wsig > 0.0) {
+        const double disc = sqrt(S * S + 4.0 * wsig * dl / rho);
+        x = S >= 0.0 ? (S + disc) / (2.0 * dl) : 2.0 * wsig / (rho * (disc - S));
+    } else {
+        x = (S - wsig / rho) / dl;
+    }
+    return fmin(fmax(x, lo), hi);
+}
+
+template <typename T, bool CHECK>
+__device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, double vsum,
+                                                double rho)
+{
+    const double a = (double)d.a[j];
+    const double S = (double)L * a + vsum;
+    const T xt = (T)prox_stream(S, L, (double)d.wsig[j], rho, d.lo, d.hi);
+    const double xn = (double)xt;
+    double part = 0.0;
+    if (CHECK) {                       // dual residual: sum_j L_j (dx_j)^2
+        const double dx = xn - (double)d.x[j];
+        part = (double)L * dx * dx;
+    }
+    d.x[j] = xt;
+    d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
+    return part;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void link_update(const Dev<T> &d, int l, int deg, double y,
+                                            double &r2, double &s2)
+{
+    const double c = (double)d.c[l], u = (double)d.u[l];
+    const double b = (double)d.b[l], zs = (double)d.zs[l];
+    const double al = d.alpha;
+    const double ps = fmax(zs - u, -c);                 // slack prox
+    const double cnt = (double)deg + 1.0;               // |l| = d_l + 1
+    const double pbar = (y + ps) / cnt;                 // link average
+    const T bt = (T)(-al * pbar + (1.0 - al) * b);
+    const T ut = (T)(u + al * pbar);
+    d.b[l] = bt;
+    d.zs[l] = (T)(al * (ps - pbar) + (1.0 - al) * zs);
+    d.u[l] = ut;
+    d.v[l] = (T)((double)bt - (double)ut);
+    if (MODE == kCheck) {
+        // ||r||^2 = sum_l |l| pbar_l^2 and, with D the change since the
+        // previous iteration, the link part of ||s||^2 / rho^2:
+        // sum_{j on l} (Dx_j - Dpbar)^2 + (Dps - Dpbar)^2
+        //   = [sum_j Dx_j^2] + d Dpbar^2 - 2 Dpbar Dy + (Dps - Dpbar)^2,
+        // the bracket being added on the stream side.
+        const double yp = d.y_prev[l], pp = d.ps_prev[l];
+        const double dpb = pbar - (yp + pp) / cnt;
+        const double dy = y - yp, dps = ps - pp;
+        r2 += cnt * pbar * pbar;
+        s2 += (double)deg * dpb * dpb - 2.0 * dpb * dy + (dps - dpb) * (dps - dpb);
+    }
+    if (MODE != kPlain) {
+        d.y_prev[l] = y;
+        d.ps_prev[l] = ps;
+    }
+}
+
+// ---- stream pass ---------------------------------------------------------
+
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(kBlock) void k_stream_pass(Dev<T> d)
+{
+    if (d.ctl->done) return;
+    __shared__ T sv[kCap];
+    __shared__ double sred[kBlock / 64];
+    const int blk = blockIdx.x;
+    const int s0 = d.sblk[blk], s1 = d.sblk[blk + 1];
+    const int e0 = d.col_ptr[s0];
+    const int cnt = d.col_ptr[s1] - e0;
+    const double rho = d.ctl->rho;
+    double part = 0.0;
+    if (cnt <= kCap) {
+        gather_stage<T>(d.row_idx + e0, d.v, sv, cnt);
+        __syncthreads();
+        const int j = s0 + (int)threadIdx.x;
+        if (j < s1) {
+            const int b = d.col_ptr[j] - e0, e = d.col_ptr[j + 1] - e0;
+            double acc = 0.0;
+            for (int k = b; k < e; ++k) acc += (double)sv[k];
+            part = stream_update<T, CHECK>(d, j, e - b, acc, rho);
+        }
+    } else {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kBlock)
+            acc += (double)d.v[ld_stream(d.row_idx + e0 + k)];
+        acc = block_sum(acc, sred);
+        if (threadIdx.x == 0) part = stream_update<T, CHECK>(d, s0, cnt, acc, rho);
+    }
+    if (CHECK) {
+        part = block_sum(part, sred);
+        if (threadIdx.x == 0) d.spart[blk] = part;
+    }
+}
+
+// ---- residual reduction, stop rule and rho balancing ---------------------
+
+template <typename T>
+__device__ void finalize(const Dev<T> &d, long long delta, int stop, double *sred)
+{
+    __threadfence();
+    double sr = 0.0, ss = 0.0;
+    for (int i = threadIdx.x; i < d.nlb; i += kBlock) {
+        sr += d.lpart[2 * i];
+        ss += d.lpart[2 * i + 1];
+    }
+    for (int i = threadIdx.x; i < d.nsb; i += kBlock) ss += d.spart[i];
+    sr = block_sum(sr, sred);
+    ss = block_sum(ss, sred);
+    if (threadIdx.x != 0) return;
+    Ctl *c = d.ctl;
+    const double rho = c->rho;
+    const long long it = c->iter + delta;
+    const double r = sqrt(sr);
+    const double s = rho * sqrt(fmax(ss, 0.0));
+    c->iter = it;
+    c->r_norm = r;
+    c->s_norm = s;
+    c->ratio = 1.0;
+    HistEntry &h = d.hist[c->nhist % kHist];
+    h.iter = it;
+    h.r_norm = r;
+    h.s_norm = s;
+    h.rho = rho;
+    c->nhist += 1;
+    if (!isfinite(r) || !isfinite(s)) {
+        c->status = PMP_ERR_NUMERIC;
+        c->done = 1;
+    } else if (stop && r < c->eps_tol && s < c->eps_tol) {
+        c->status = PMP_OK;
+        c->done = 1;
+    } else if (c->adapt_every > 0 && it % c->adapt_every == 0) {
+        double rn = rho;
+        if (r > c->mu * s) rn = c->gamma * rho;
+        else if (s > c->mu * r) rn = rho / c->gamma;
+        c->ratio = rho / rn;
+        c->rho = rn;
+    }
+    c->arrive = 0u;
+}
+
+// ---- link pass -------------------------------------------------------------
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d, long long delta, int stop)
+{
+    if (d.ctl->done) return;
+    __shared__ T sx[kCap];
+    __shared__ double sred[kBlock / 64];
+    __shared__ int s_last;
+    const int blk = blockIdx.x;
+    const int l0 = d.lblk[blk], l1 = d.lblk[blk + 1];
+    const int e0 = d.row_ptr[l0];
+    const int cnt = d.row_ptr[l1] - e0;
+    double r2 = 0.0, s2 = 0.0;
+    if (cnt <= kCap) {
+        gather_stage<T>(d.col_idx + e0, d.x, sx, cnt);
+        __syncthreads();
+        const int l = l0 + (int)threadIdx.x;
+        if (l < l1) {
+            const int b = d.row_ptr[l] - e0, e = d.row_ptr[l + 1] - e0;
+            double acc = 0.0;
+            for (int k = b; k < e; ++k) acc += (double)sx[k];
+            link_update<T, MODE>(d, l, e - b, acc, r2, s2);
+        }
+    } else {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kBlock)
+            acc += (double)d.x[ld_stream(d.col_idx + e0 + k)];
+        acc = block_sum(acc, sred);
+        if (threadIdx.x == 0) link_update<T, MODE>(d, l0, cnt, acc, r2, s2);
+    }
+    if (MODE == kCheck) {
+        r2 = block_sum(r2, sred);
+        s2 = block_sum(s2, sred);
+        if (threadIdx.x == 0) {
+            d.lpart[2 * blk] = r2;
+            d.lpart[2 * blk + 1] = s2;
+            __threadfence();
+            const unsigned prev = atomicAdd(&d.ctl->arrive, 1u);
+            s_last = prev == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (s_last) finalize<T>(d, delta, stop, sred);
+    }
+}
+
+// u <- (rho_old / rho_new) u after a balancing step (eq. (7)); v = b - u.
+template <typename T>
+__global__ void k_rescale(Dev<T> d)
+{
+    const double ratio = d.ctl->ratio;
+    if (ratio == 1.0) return;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += gridDim.x * blockDim.x) {
+        const T ut = (T)((double)d.u[l] * ratio);
+        d.u[l] = ut;
+        d.v[l] = (T)((double)d.b[l] - (double)ut);
+    }
+}
+
+template <typename T>
+__global__ void k_refresh_v(Dev<T> d)
+{
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += gridDim.x * blockDim.x)
+        d.v[l] = (T)((double)d.b[l] - (double)d.u[l]);
+}
+
+// ---- setup ------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_init_state(Dev<T> d, const T *c_in, const T *w_in, const uint8_t *util)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
+        const T w = w_in[j];
+        const_cast<T *>(d.wsig)[j] = util[j] ? -w : w;
+        d.a[j] = T(0);
+        d.x[j] = T(0);
+    }
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
+        const_cast<T *>(d.c)[l] = c_in[l];
+        d.b[l] = T(0);
+        d.zs[l] = T(0);
+        d.u[l] = T(0);
+        d.v[l] = T(0);
+        d.y_prev[l] = 0.0;
+        d.ps_prev[l] = 0.0;
+    }
+}
+
+template <typename T>
+__global__ void k_check_vectors(const T *c, const T *w, const uint8_t *util, int m, int n,
+                                Ctl *ctl)
+{
+    const int stride = gridDim.x * blockDim.x;
+    unsigned f = 0;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < m; l += stride) {
+        const double v = (double)c[l];
+        if (!(v > 0.0) || !isfinite(v)) f |= kErrCap;
+    }
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const double v = (double)w[j];
+        if (!(v > 0.0) || !isfinite(v)) f |= kErrWeight;
+        if (util[j] > 1) f |= kErrUtility;
+    }
+    if (f) atomicOr(&ctl->flags, f);
+}
+
+__global__ void k_validate_csr(const int *row_ptr, const int *col_idx, int m, int n,
+                               long long nnz, Ctl *ctl)
+{
+    const int stride = gridDim.x * blockDim.x;
+    unsigned f = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        if (row_ptr[0] != 0 || (long long)row_ptr[m] != nnz) f |= kErrRowPtr;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < m; l += stride) {
+        const long long b = row_ptr[l], e = row_ptr[l + 1];
+        if (b < 0 || e < b || e > nnz) {
+            f |= kErrRowPtr;
+            continue;
+        }
+        int prev = -1;
+        for (long long k = b; k < e; ++k) {
+            const int j = col_idx[k];
+            if (j < 0 || j >= n) f |= kErrColRange;
+            else if (j <= prev) f |= kErrColOrder;
+            prev = j;
+        }
+    }
+    if (f) atomicOr(&ctl->flags, f);
+}
+
+__global__ void k_histogram(const int *col_idx, long long nnz, int *count)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nnz; k += stride)
+        atomicAdd(&count[col_idx[k]], 1);
+}
+
+constexpr int kScanPer = 8;                      // elements per thread
+constexpr int kScanTile = kBlock * kScanPer;     // elements per workgroup
+
+__device__ int block_excl_scan_int(int v, int *sh, int *total)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int t = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int incl = sh[threadIdx.x];
+    *total = sh[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int *in, int n, int *bsum)
+{
+    __shared__ int sh[kBlock];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    int s = 0;
+    for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
+        const long long k = base + i;
+        if (k < n) s += in[k];
+    }
+    int total;
+    block_excl_scan_int(s, sh, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_bsums(int *bsum, int nb)
+{
+    __shared__ int sh[kBlock];
+    int carry = 0;
+    for (int base = 0; base < nb; base += kBlock) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        int total;
+        const int ex = block_excl_scan_int(v, sh, &total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+}
+
+// out[0] = 0, out[k + 1] = in[0] + ... + in[k]
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int *in, int n, const int *boff,
+                                                       int *out)
+{
+    __shared__ int sh[kBlock];
+    const long long base = (long long)blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const long long k = base + i;
+        v[i] = k < n ? in[k] : 0;
+        s += v[i];
+    }
+    int total;
+    int run = boff[blockIdx.x] + block_excl_scan_int(s, sh, &total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const long long k = base + i;
+        run += v[i];
+        if (k < n) out[k + 1] = run;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+}
+
+__global__ void k_scatter(const int *row_ptr, const int *col_idx, int m, const int *col_ptr,
+                          int *fill, int *row_idx)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < m; l += stride) {
+        for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) {
+            const int j = col_idx[k];
+            row_idx[col_ptr[j] + atomicAdd(&fill[j], 1)] = l;
+        }
+    }
+}
+
+// Sort every column's links ascending (the scatter order is arbitrary).
+__global__ void k_sort_columns(const int *col_ptr, int n, int *row_idx)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const int b = col_ptr[j], e = col_ptr[j + 1];
+        for (int i = b + 1; i < e; ++i) {
+            const int key = row_idx[i];
+            int k = i - 1;
+            while (k >= b && row_idx[k] > key) {
+                row_idx[k + 1] = row_idx[k];
+                --k;
+            }
+            row_idx[k + 1] = key;
+        }
+    }
+}
+
+__global__ void k_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl)
+{
+    const int stride = gridDim.x * blockDim.x;
+    unsigned f = 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride)
+        if (col_ptr[j + 1] == col_ptr[j] && isinf(hi)) f |= kErrEmptyRoute;
+    if (f) atomicOr(&ctl->flags, f);
+}
+
+__global__ void k_fill_int(int *p, int value, size_t count)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += stride)
+        p[i] = value;
+}
+
+__global__ void k_ctl_init(Ctl *c, double rho, double eps_tol, double mu, double gamma,
+                           int adapt_every)
+{
+    c->rho = rho;
+    c->ratio = 1.0;
+    c->r_norm = 0.0;
+    c->s_norm = 0.0;
+    c->eps_tol = eps_tol;
+    c->mu = mu;
+    c->gamma = gamma;
+    c->iter = 0;
+    c->nhist = 0;
+    c->adapt_every = adapt_every;
+    c->done = 0;
+    c->status = PMP_OK;
+    c->arrive = 0u;
+    c->flags = 0u;
+}
+
+__global__ void k_ctl_clear_done(Ctl *c)
+{
+    c->done = 0;
+    c->status = PMP_OK;
+}
+
+template <typename T>
+__global__ void k_solution(Dev<T> d, T *x, T *lambda, T *slack)
+{
+    const int stride = gridDim.x * blockDim.x;
+    const double rho = d.ctl->rho;
+    if (x)
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) x[j] = d.x[j];
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
+        if (lambda) lambda[l] = (T)(rho * (double)d.u[l]);
+        if (slack) slack[l] = (T)(d.ps_prev[l] + (double)d.c[l]);
+    }
+}
+
+template <typename T>
+__global__ void k_copy_capacity(Dev<T> d, const T *c_new)
+{
+    const int stride = gridDim.x * blockDim.x;
+    unsigned f = 0;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
+        const T v = c_new[l];
+        if (!((double)v > 0.0) || !isfinite((double)v)) f |= kErrCap;
+        const_cast<T *>(d.c)[l] = v;
+    }
+    if (f) atomicOr(&d.ctl->flags, f);
+}
+
+inline int grid_for(long long count, int block = kBlock, int cap = 65536)
+{
+    long long g = (count + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+// ---- launchers -----------------------------------------------------------
+
+template <typename T>
+void launch_stream_pass(const Dev<T> &d, bool check, hipStream_t s)
+{
+    if (d.nsb == 0) return;
+    if (check) hipLaunchKernelGGL((k_stream_pass<T, true>), dim3(d.nsb), dim3(kBlock), 0, s, d);
+    else hipLaunchKernelGGL((k_stream_pass<T, false>), dim3(d.nsb), dim3(kBlock), 0, s, d);
+}
+
+template <typename T>
+void launch_link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t s)
+{
+    if (d.nlb == 0) return;
+    switch (mode) {
+    case kPlain:
+        hipLaunchKernelGGL((k_link_pass<T, kPlain>), dim3(d.nlb), dim3(kBlock), 0, s, d, delta, stop);
+        break;
+    case kSave:
+        hipLaunchKernelGGL((k_link_pass<T, kSave>), dim3(d.nlb), dim3(kBlock), 0, s, d, delta, stop);
+        break;
+    default:
+        hipLaunchKernelGGL((k_link_pass<T, kCheck>), dim3(d.nlb), dim3(kBlock), 0, s, d, delta, stop);
+        break;
+    }
+}
+
+template <typename T>
+void launch_rescale(const Dev<T> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_rescale<T>), dim3(grid_for(d.m, kBlock, 4096)), dim3(kBlock), 0, s, d);
+}
+
+template <typename T>
+void launch_refresh_v(const Dev<T> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_refresh_v<T>), dim3(grid_for(d.m, kBlock, 4096)), dim3(kBlock), 0, s, d);
+}
+
+template <typename T>
+void launch_init_state(const Dev<T> &d, const T *c_in, const T *w_in, const uint8_t *util,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init_state<T>), dim3(grid_for(d.n > d.m ? d.n : d.m, kBlock, 16384)),
+                       dim3(kBlock), 0, s, d, c_in, w_in, util);
+}
+
+template <typename T>
+void launch_check_vectors(const T *c, const T *w, const uint8_t *util, int m, int n, Ctl *ctl,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL((k_check_vectors<T>), dim3(grid_for(n > m ? n : m, kBlock, 16384)),
+                       dim3(kBlock), 0, s, c, w, util, m, n, ctl);
+}
+
+template <typename T>
+void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_solution<T>), dim3(grid_for(d.n > d.m ? d.n : d.m, kBlock, 16384)),
+                       dim3(kBlock), 0, s, d, x, lambda, slack);
+}
+
+template <typename T>
+void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_copy_capacity<T>), dim3(grid_for(d.m, kBlock, 16384)), dim3(kBlock), 0,
+                       s, d, c_new);
+}
+
+void launch_validate_csr(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
+                         Ctl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_validate_csr, dim3(grid_for(m, kBlock, 16384)), dim3(kBlock), 0, s,
+                       row_ptr, col_idx, m, n, nnz, ctl);
+}
+
+size_t transpose_scratch_ints(int n)
+{
+    const size_t nb = ((size_t)n + kScanTile - 1) / kScanTile;
+    return (size_t)n + nb + 1;
+}
+
+void launch_transpose(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
+                      int *col_ptr, int *row_idx, int *tmp, hipStream_t s)
+{
+    int *count = tmp;
+    const int nb = (int)(((long long)n + kScanTile - 1) / kScanTile);
+    int *bsum = tmp + n;
+    launch_fill_int(count, 0, (size_t)n, s);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_histogram, dim3(grid_for(nnz, kBlock, 65536)), dim3(kBlock), 0, s,
+                           col_idx, nnz, count);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, count, n, bsum);
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsum, nb);
+        hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, count, n, bsum, col_ptr);
+    } else {
+        launch_fill_int(col_ptr, 0, 1, s);
+    }
+    launch_fill_int(count, 0, (size_t)n, s);
+    if (m > 0)
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, kBlock, 65536)), dim3(kBlock), 0, s,
+                           row_ptr, col_idx, m, col_ptr, count, row_idx);
+    if (n > 0)
+        hipLaunchKernelGGL(k_sort_columns, dim3(grid_for(n, kBlock, 65536)), dim3(kBlock), 0, s,
+                           col_ptr, n, row_idx);
+}
+
+void launch_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl, hipStream_t s)
+{
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_check_routes, dim3(grid_for(n, kBlock, 16384)), dim3(kBlock), 0, s,
+                       col_ptr, n, hi, ctl);
+}
+
+void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gamma,
+                     int adapt_every, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, ctl, rho, eps_tol, mu, gamma,
+                       adapt_every);
+}
+
+void launch_ctl_clear_done(Ctl *ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_clear_done, dim3(1), dim3(1), 0, s, ctl);
+}
+
+void launch_fill_int(int *p, int value, size_t count, hipStream_t s)
+{
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for((long long)count, kBlock, 16384)), dim3(kBlock),
+                       0, s, p, value, count);
+}
+
+#define PMP_INSTANTIATE(T)                                                                  \
+    template void launch_stream_pass<T>(const Dev<T> &, bool, hipStream_t);                \
+    template void launch_link_pass<T>(const Dev<T> &, int, long long, int, hipStream_t);   \
+    template void launch_rescale<T>(const Dev<T> &, hipStream_t);                           \
+    template void launch_refresh_v<T>(const Dev<T> &, hipStream_t);                         \
+    template void launch_init_state<T>(const Dev<T> &, const T *, const T *,               \
+                                       const uint8_t *, hipStream_t);                       \
+    template void launch_check_vectors<T>(const T *, const T *, const uint8_t *, int, int, \
+                                          Ctl *, hipStream_t);                              \
+    template void launch_solution<T>(const Dev<T> &, T *, T *, T *, hipStream_t);           \
+    template void launch_copy_capacity<T>(const Dev<T> &, const T *, hipStream_t);
+
+PMP_INSTANTIATE(float)
+PMP_INSTANTIATE(double)
+
+}  // namespace pmp

@@ -1,0 +1,248 @@
+"""Python binding of the PMP C ABI (include/pmp.h).
+
+Argument marshalling only: every step of the solver runs in libpmp.so's HIP
+kernels.  PyTorch supplies device memory (the workspace and the problem
+arrays) and the stream.  The functions keep the C names; `Solver` bundles
+them for one instance.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+PMP_OK, PMP_ERR_INVALID, PMP_ERR_SHAPE, PMP_ERR_NOMEM, PMP_ERR_HIP, PMP_ERR_NUMERIC, \
+    PMP_NOT_CONVERGED, PMP_ERR_STATE = range(8)
+PMP_F32, PMP_F64 = 0, 1
+PMP_MEM_HOST, PMP_MEM_DEVICE = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpmp.so")
+_lib = None
+
+
+class PMPError(RuntimeError):
+    def __init__(self, status, where, detail):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+class pmp_problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("utility", ctypes.c_void_p), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double), ("dtype", ctypes.c_int), ("memory", ctypes.c_int)]
+
+
+class pmp_params(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("mu", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("eps_abs", ctypes.c_double), ("adapt_every", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+
+
+class pmp_result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("r_norm", ctypes.c_double),
+                ("s_norm", ctypes.c_double), ("eps_tol", ctypes.c_double),
+                ("rho", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "pmp_params_default": [ctypes.POINTER(pmp_params)],
+    "pmp_workspace_size": [ctypes.POINTER(pmp_problem), ctypes.POINTER(pmp_params),
+                           ctypes.POINTER(ctypes.c_size_t)],
+    "pmp_setup": [ctypes.POINTER(pmp_problem), ctypes.POINTER(pmp_params), _P,
+                  ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "pmp_iterate": [_P, ctypes.c_int32],
+    "pmp_residuals": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                      ctypes.POINTER(ctypes.c_int64)],
+    "pmp_solve": [_P, ctypes.POINTER(pmp_result)],
+    "pmp_get_solution": [_P, _P, _P, _P],
+    "pmp_state_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "pmp_get_state": [_P, _P],
+    "pmp_set_state": [_P, _P],
+    "pmp_update_capacity": [_P, _P],
+    "pmp_device_views": [_P] + [ctypes.POINTER(_P)] * 6,
+    "pmp_destroy": [_P],
+}
+
+
+def exported_symbols():
+    """Names the C ABI exports (include/pmp.h)."""
+    return sorted(list(_SIGNATURES) + ["pmp_status_string", "pmp_last_error"])
+
+
+def load_library(require_torch: bool = True):
+    """Load libpmp.so.  torch is imported first so that the library binds to
+    the HIP runtime torch already loaded (one runtime per process)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if require_torch:
+        import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.pmp_status_string.argtypes = [ctypes.c_int]
+    lib.pmp_status_string.restype = ctypes.c_char_p
+    lib.pmp_last_error.argtypes = []
+    lib.pmp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status, where, allow=(PMP_OK,)):
+    if status not in allow:
+        lib = load_library()
+        raise PMPError(status, where, lib.pmp_last_error().decode())
+    return status
+
+
+def params_default(**overrides) -> pmp_params:
+    p = pmp_params()
+    _check(load_library().pmp_params_default(ctypes.byref(p)), "pmp_params_default")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _device_array(torch, a, dtype, device):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dtype, device=device)
+
+
+class Solver:
+    """One NUM instance resident on the GPU.
+
+    `inst` has m, n, row_ptr, col_idx (int32 CSR of R), c, w, utility, lo,
+    hi (see paper_2509_10722_amd.instances.Instance).  dtype is torch.float32
+    or torch.float64.  With memory="device" the arrays are first placed in
+    device tensors (the boundary then reads device memory); with "host" the
+    library copies them from host memory.
+    """
+
+    def __init__(self, inst, dtype=None, params=None, device="cuda", memory="device", **kw):
+        import torch
+        lib = load_library()
+        self.torch = torch
+        self.dtype = dtype or torch.float32
+        self.device = torch.device(device)
+        self.m, self.n = int(inst.m), int(inst.n)
+        self.nnz = int(inst.row_ptr[-1])
+        npdt = np.float32 if self.dtype == torch.float32 else np.float64
+        self.params = params or params_default(**kw)
+        dt = PMP_F32 if self.dtype == torch.float32 else PMP_F64
+        if memory == "device":
+            arrs = [_device_array(torch, inst.row_ptr, torch.int32, self.device),
+                    _device_array(torch, inst.col_idx, torch.int32, self.device),
+                    _device_array(torch, inst.c, self.dtype, self.device),
+                    _device_array(torch, inst.w, self.dtype, self.device),
+                    _device_array(torch, inst.utility, torch.uint8, self.device)]
+            ptrs = [a.data_ptr() for a in arrs]
+            mem = PMP_MEM_DEVICE
+        else:
+            arrs = [np.ascontiguousarray(inst.row_ptr, dtype=np.int32),
+                    np.ascontiguousarray(inst.col_idx, dtype=np.int32),
+                    np.ascontiguousarray(inst.c, dtype=npdt),
+                    np.ascontiguousarray(inst.w, dtype=npdt),
+                    np.ascontiguousarray(inst.utility, dtype=np.uint8)]
+            ptrs = [a.ctypes.data for a in arrs]
+            mem = PMP_MEM_HOST
+        self.problem = pmp_problem(self.m, self.n, self.nnz, *ptrs, float(inst.lo),
+                                   float(inst.hi), dt, mem)
+        nbytes = ctypes.c_size_t()
+        _check(lib.pmp_workspace_size(ctypes.byref(self.problem), ctypes.byref(self.params),
+                                      ctypes.byref(nbytes)), "pmp_workspace_size")
+        self.workspace = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.pmp_setup(ctypes.byref(self.problem), ctypes.byref(self.params),
+                             self.workspace.data_ptr(), nbytes.value, self.stream.cuda_stream,
+                             ctypes.byref(h)), "pmp_setup")
+        self.handle = h
+        del arrs
+        self.lib = lib
+
+    # -- C calls -----------------------------------------------------------
+    def iterate(self, k: int):
+        _check(self.lib.pmp_iterate(self.handle, int(k)), "pmp_iterate")
+
+    def residuals(self):
+        r, s, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.pmp_residuals(self.handle, ctypes.byref(r), ctypes.byref(s),
+                                      ctypes.byref(it)), "pmp_residuals")
+        return r.value, s.value, it.value
+
+    def solve(self):
+        res = pmp_result()
+        st = self.lib.pmp_solve(self.handle, ctypes.byref(res))
+        _check(st, "pmp_solve", allow=(PMP_OK, PMP_NOT_CONVERGED))
+        return {"iterations": res.iterations, "r_norm": res.r_norm, "s_norm": res.s_norm,
+                "eps_tol": res.eps_tol, "rho": res.rho, "converged": st == PMP_OK}
+
+    def solution(self):
+        t = self.torch
+        x = t.empty(self.n, dtype=self.dtype, device=self.device)
+        lam = t.empty(self.m, dtype=self.dtype, device=self.device)
+        slack = t.empty(self.m, dtype=self.dtype, device=self.device)
+        _check(self.lib.pmp_get_solution(self.handle, x.data_ptr() if self.n else None,
+                                         lam.data_ptr(), slack.data_ptr()), "pmp_get_solution")
+        return x, lam, slack
+
+    def state_size(self):
+        b = ctypes.c_size_t()
+        _check(self.lib.pmp_state_size(self.handle, ctypes.byref(b)), "pmp_state_size")
+        return b.value
+
+    def get_state(self):
+        buf = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device)
+        _check(self.lib.pmp_get_state(self.handle, buf.data_ptr()), "pmp_get_state")
+        return buf
+
+    def set_state(self, buf):
+        _check(self.lib.pmp_set_state(self.handle, buf.data_ptr()), "pmp_set_state")
+
+    def update_capacity(self, c_new):
+        c = self.torch.as_tensor(c_new).to(dtype=self.dtype, device=self.device).contiguous()
+        _check(self.lib.pmp_update_capacity(self.handle, c.data_ptr()), "pmp_update_capacity")
+
+    def views(self):
+        """Zero-copy tensors over the internal x, u, a, b, zs, v."""
+        ptrs = [ctypes.c_void_p() for _ in range(6)]
+        _check(self.lib.pmp_device_views(self.handle, *[ctypes.byref(p) for p in ptrs]),
+               "pmp_device_views")
+        sizes = [self.n, self.m, self.n, self.m, self.m, self.m]
+        names = ["x", "u", "a", "b", "zs", "v"]
+        out = {}
+        esz = 4 if self.dtype == self.torch.float32 else 8
+        for nm, p, sz in zip(names, ptrs, sizes):
+            out[nm] = _tensor_from_ptr(self.torch, p.value, sz, self.dtype, self.device,
+                                       self.workspace, esz)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pmp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _tensor_from_ptr(torch, ptr, count, dtype, device, workspace, esz):
+    """View `count` elements at device address `ptr` inside `workspace`."""
+    base = workspace.data_ptr()
+    off = ptr - base
+    if off < 0 or off + count * esz > workspace.numel():
+        raise ValueError("pointer outside the workspace")
+    return workspace[off: off + count * esz].view(dtype)

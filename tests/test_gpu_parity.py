@@ -1,0 +1,257 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Equal-iteration comparisons use normwise relative error on x and on the link
+prices lambda: <= 1e-10 for the FP64 path and <= 1e-5 for the FP32 path
+(FP32 storage, FP64 accumulation; an element-wise gate would fail on rates
+near zero whose absolute error is tiny).  The FP32 runs give the oracle the
+FP32-rounded c and w, so both solve the same problem.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import optimality as opt
+from paper_2509_10722_amd import instances as I
+from tests.gpu_util import host, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2509_10722_amd.pmp import PMPError, Solver  # noqa: E402
+
+F64_TOL = 1e-10
+F32_TOL = 1e-5
+
+
+def _run_gpu(inst, K, dtype, **kw):
+    s = Solver(inst, dtype=dtype, **kw)
+    s.iterate(K)
+    r, sn, it = s.residuals()
+    x, lam, slack = s.solution()
+    out = {"x": host(x), "lam": host(lam), "slack": host(slack), "r": r, "s": sn, "it": it}
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("adapt", [0, 50])
+def test_tiny_fp64_equal_iterations(adapt):
+    inst = I.tiny()
+    K = 2000
+    g = _run_gpu(inst, K, torch.float64, adapt_every=adapt)
+    o = oracle.run(inst, K, adapt_every=adapt)
+    print(f"tiny fp64 adapt={adapt}: x {rel(g['x'], o['x']):.2e} lam {rel(g['lam'], o['lam']):.2e}")
+    assert g["it"] == K
+    assert rel(g["x"], o["x"]) <= F64_TOL
+    assert rel(g["lam"], o["lam"]) <= F64_TOL
+    assert rel(g["slack"], o["slack"]) <= F64_TOL
+    assert abs(g["r"] - o["r_norm"]) <= 1e-8 * max(o["r_norm"], 1e-12)
+    assert abs(g["s"] - o["s_norm"]) <= 1e-6 * max(o["s_norm"], 1e-12)
+
+
+def test_tiny_fp32_equal_iterations():
+    inst = I.tiny().rounded(np.float32)
+    K = 2000
+    g = _run_gpu(inst, K, torch.float32)
+    o = oracle.run(inst, K)
+    ex, el = rel(g["x"], o["x"]), rel(g["lam"], o["lam"])
+    print(f"tiny fp32: x {ex:.2e} lam {el:.2e}")
+    assert ex <= F32_TOL and el <= F32_TOL
+
+
+def test_medium_fp32_equal_iterations():
+    inst = I.medium().rounded(np.float32)
+    K = 100
+    g = _run_gpu(inst, K, torch.float32)
+    o = oracle.run(inst, K)
+    ex, el = rel(g["x"], o["x"]), rel(g["lam"], o["lam"])
+    print(f"medium fp32 K={K}: x {ex:.2e} lam {el:.2e}")
+    assert ex <= F32_TOL and el <= F32_TOL
+    assert abs(g["r"] - o["r_norm"]) <= 1e-3 * o["r_norm"]
+
+
+def _edge_instance():
+    """Ragged shapes: a route longer than one workgroup's LDS stage, a link
+    on more streams than that, links no stream uses, a stream with an empty
+    route (finite hi), single-link streams."""
+    rng = np.random.default_rng(11)
+    m, n = 6000, 9000
+    link, stream = [], []
+    long_route = rng.choice(m - 10, 5000, replace=False)         # stream 0
+    link += list(long_route); stream += [0] * 5000
+    busy = m - 1                                                  # link on 4500 streams
+    for j in range(1, 4501):
+        link.append(busy); stream.append(j)
+    for j in range(1, n - 1):                                     # stream n-1: empty route
+        L = int(rng.integers(1, 4))
+        for l in rng.choice(m - 10, L, replace=False):
+            if not (j <= 4500 and l == busy):
+                link.append(int(l)); stream.append(j)
+    pairs = np.unique(np.array([link, stream]).T, axis=0)
+    row_ptr, col_idx = I.csr_from_pairs(m, n, pairs[:, 0], pairs[:, 1])
+    util = (rng.random(n) < 0.3).astype(np.uint8)
+    w = np.where(util == 0, rng.uniform(0.5, 2, n), rng.uniform(0.1, 1, n))
+    return I.Instance("edge", m, n, row_ptr, col_idx, rng.uniform(1, 50, m), w, util, 0.0, 20.0)
+
+
+def test_edge_shapes_fp64():
+    inst = _edge_instance()
+    deg = np.diff(inst.row_ptr)
+    assert deg.max() > 4096 and (deg == 0).sum() >= 5
+    assert np.bincount(inst.col_idx, minlength=inst.n).max() > 4096
+    K = 300
+    g = _run_gpu(inst, K, torch.float64)
+    o = oracle.run(inst, K)
+    assert rel(g["x"], o["x"]) <= F64_TOL and rel(g["lam"], o["lam"]) <= F64_TOL
+    assert g["x"][-1] == 20.0                                     # empty route -> hi
+
+
+def test_paper_example_and_single_link():
+    for inst, (x_ref, lam_ref) in [
+        (I.paper_example(1.0, 3.0, hi=1e3), opt.paper_example(1.0, 3.0)),
+        (I.single_link([0.5, 1.0, 1.7], [0, 0, 0], 6.0, hi=1e3),
+         (np.array([0.5, 1.0, 1.7]) * 6.0 / 3.2, np.array([3.2 / 6.0])))]:
+        s = Solver(inst, dtype=torch.float64, eps_abs=1e-12, max_iter=50000)
+        res = s.solve()
+        x, lam, _ = s.solution()
+        s.close()
+        assert res["converged"]
+        np.testing.assert_allclose(host(x), x_ref, rtol=1e-8)
+        np.testing.assert_allclose(host(lam), lam_ref, rtol=1e-7)
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_solve_matches_oracle_stop(dtype_name):
+    dtype = getattr(torch, dtype_name)
+    inst = I.tiny() if dtype_name == "float64" else I.tiny().rounded(np.float32)
+    s = Solver(inst, dtype=dtype)
+    res = s.solve()
+    x, lam, slack = s.solution()
+    s.close()
+    o = oracle.run(inst, 100000, stop=True)
+    assert res["converged"] and o["converged"]
+    print(f"{dtype_name}: gpu {res['iterations']} it, oracle {o['iterations']} it")
+    if dtype_name == "float64":
+        assert res["iterations"] == o["iterations"]
+        assert rel(host(x), o["x"]) <= F64_TOL
+    else:
+        assert abs(res["iterations"] - o["iterations"]) <= 20
+    rep = opt.kkt_report(inst, host(x), host(lam))
+    assert rep["primal_infeas"] < 1e-2 and rep["rel_gap"] < 1e-2
+
+
+def test_zsum_invariant_compact_form():
+    """(R a)_l + d_l b_l + zs_l = 0: the link-side copies of each link sum to
+    zero after every z-update (Section III-C's g_l)."""
+    inst = I.tiny()
+    s = Solver(inst, dtype=torch.float64)
+    s.iterate(137)
+    v = s.views()
+    a, b, zs = host(v["a"]), host(v["b"]), host(v["zs"])
+    s.close()
+    Ra = opt.csr_matvec(inst, a)
+    d = np.diff(inst.row_ptr)
+    resid = Ra + d * b + zs
+    scale = np.abs(Ra) + np.abs(d * b) + np.abs(zs) + 1e-30
+    assert np.max(np.abs(resid) / scale) < 1e-12
+
+
+def test_bitwise_deterministic():
+    inst = I.medium(scale=0.1)
+    xs = []
+    for _ in range(2):
+        s = Solver(inst, dtype=torch.float32)
+        s.iterate(300)
+        x, lam, _ = s.solution()
+        xs.append((host(x), host(lam), s.residuals()))
+        s.close()
+    assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
+    assert xs[0][2] == xs[1][2]
+
+
+def test_iterate_chunking_does_not_change_iterates():
+    inst = I.tiny()
+    a = Solver(inst, dtype=torch.float64)
+    a.iterate(7); a.iterate(60); a.iterate(33)
+    b = Solver(inst, dtype=torch.float64)
+    b.iterate(100)
+    xa, la, _ = a.solution()
+    xb, lb, _ = b.solution()
+    assert torch.equal(xa, xb) and torch.equal(la, lb)
+    assert a.residuals() == b.residuals()
+    a.close(); b.close()
+
+
+def test_state_roundtrip_and_warm_start():
+    inst = I.tiny()
+    s = Solver(inst, dtype=torch.float64)
+    s.iterate(40)
+    st = s.get_state()
+    s.iterate(25)
+    x1, l1, _ = s.solution()
+    s.set_state(st)
+    s.iterate(25)
+    x2, l2, _ = s.solution()
+    assert torch.equal(x1, x2) and torch.equal(l1, l2)
+    s.close()
+
+
+def test_capacity_degradation_warm_start():
+    """Section V-D: re-solve after a capacity cut, cold vs warm."""
+    inst = I.tiny()
+    rng = np.random.default_rng(5)
+    c_new = inst.c * np.where(rng.random(inst.m) < 0.25, 0.5, 1.0)
+    warm = Solver(inst, dtype=torch.float64)
+    assert warm.solve()["converged"]
+    warm.update_capacity(c_new)
+    rw = warm.solve()
+    xw, lw, _ = warm.solution()
+    warm.close()
+    deg = I.Instance(inst.name, inst.m, inst.n, inst.row_ptr, inst.col_idx, c_new, inst.w,
+                     inst.utility, inst.lo, inst.hi)
+    cold = Solver(deg, dtype=torch.float64)
+    rc = cold.solve()
+    cold.close()
+    assert rw["converged"] and rc["converged"]
+    assert rw["iterations"] < rc["iterations"]
+    rep = opt.kkt_report(deg, host(xw), host(lw))
+    assert rep["primal_infeas"] < 1e-2 and rep["rel_gap"] < 1e-2
+
+
+@pytest.mark.parametrize("mutate,text", [
+    (lambda i: i.col_idx.__setitem__(1, i.col_idx[0]), "strictly increasing"),
+    (lambda i: i.col_idx.__setitem__(0, i.n + 3), "out of range"),
+    (lambda i: i.c.__setitem__(3, 0.0), "capacities"),
+    (lambda i: i.c.__setitem__(3, np.nan), "capacities"),
+    (lambda i: i.w.__setitem__(2, -1.0), "weights"),
+    (lambda i: i.utility.__setitem__(2, 7), "utility"),
+])
+@pytest.mark.parametrize("memory", ["device", "host"])
+def test_validation_errors(mutate, text, memory):
+    inst = I.tiny()
+    inst.col_idx = inst.col_idx.copy(); inst.c = inst.c.copy()
+    inst.w = inst.w.copy(); inst.utility = inst.utility.copy()
+    mutate(inst)
+    with pytest.raises(PMPError) as e:
+        Solver(inst, dtype=torch.float32, memory=memory)
+    assert e.value.status == 1 and text in str(e.value)
+
+
+def test_empty_route_needs_finite_hi():
+    inst = I.single_link([1.0, 1.0], [0, 0], 2.0)
+    inst = I.Instance("e", 1, 3, inst.row_ptr, inst.col_idx, inst.c, np.ones(3),
+                      np.zeros(3, np.uint8), 0.0, math.inf)
+    with pytest.raises(PMPError) as e:
+        Solver(inst, dtype=torch.float64)
+    assert "empty route" in str(e.value)
+
+
+def test_host_and_device_inputs_agree():
+    inst = I.tiny()
+    a = _run_gpu(inst, 200, torch.float32, memory="host")
+    b = _run_gpu(inst, 200, torch.float32, memory="device")
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["lam"], b["lam"])
