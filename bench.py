@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""PMP throughput on one MI355X: iterations per second and achieved HBM
+bandwidth on the large synthetic NUM instance, plus time to the 1e-4 stop
+rule, with the FP64 CPU oracle timed beside it.
+
+One step = one PMP iteration: the stream pass (CSC gather, prox, relaxation)
+and the link pass (CSR gather, slack prox, averaging, dual update), with the
+residual check every 10 iterations and rho balancing every 50, replayed as
+captured graphs by pmp_solve (stop rule disabled in the timed region).
+
+Workload "large": m = 5e6 links, n = 2e7 streams, route lengths from a
+discrete power law P(L) ~ L^-2.5 on {3..40}, capacities lognormal(2, 1), all
+log utilities w ~ U[0.5, 2], box [0, max c]; FP32 storage, int32 indices.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "PMP iters/sec + achieved HBM GB/s at n=2e7; time to 1e-4 rel. residual"
+KERNEL_SRC = os.path.join(ROOT, "paper_2509_10722_amd", "csrc", "pmp_kernels.hip")
+
+
+def bytes_model(n, m, nnz):
+    """Compulsory bytes per launch: every array touched once, gathered
+    vectors counted once, FP32 values and int32 indices."""
+    stream = 4 * (n + 1) + 4 * nnz + 4 * m + 4 * n + 8 * n + 4 * n   # col_ptr, row_idx, v, w, a r/w, x w
+    link = 4 * (m + 1) + 4 * nnz + 4 * n + 4 * m + 3 * 8 * m + 4 * m  # row_ptr, col_idx, x, c, u/b/zs r/w, v w
+    return {"stream": stream, "link": link, "iteration": stream + link}
+
+
+def source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """Counter-measured HBM bytes per launch from profiles/, if taken on the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != source_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="large")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--kernel-iters", type=int, default=40)
+    ap.add_argument("--tol-max-iter", type=int, default=20000)
+    ap.add_argument("--no-tol", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_10722_amd import instances
+    from paper_2509_10722_amd.pmp import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    inst = instances.make(args.config, scale=args.scale)
+    gen_s = time.perf_counter() - t0
+    st = inst.stats()
+    log(f"[bench] instance {args.config}: {st} (generated in {gen_s:.1f} s)")
+    inst32 = inst.rounded(np.float32)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver = Solver(inst32, dtype=torch.float32, eps_abs=0.0, max_iter=max(1, args.warmup))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] setup {setup_s:.2f} s")
+
+    solver.update_params(eps_abs=0.0, max_iter=max(1, args.warmup))
+    solver.solve()
+    solver.update_params(eps_abs=0.0, max_iter=args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = solver.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ips = args.steps / dt
+    log(f"[bench] timed {args.steps} iterations in {dt:.3f} s: {ips:.1f} it/s, "
+        f"r {res['r_norm']:.3e} s {res['s_norm']:.3e}")
+
+    kt = solver.time_kernels(args.kernel_iters)
+    log(f"[bench] per-kernel ms (HIP events): {kt}")
+    bm = bytes_model(inst.n, inst.m, inst.nnz)
+    dom = "link" if kt["link"] >= kt["stream"] else "stream"
+    achieved = bm[dom] / (kt[dom] * 1e-3) / 1e9
+    kname = {"link": "link_pass", "stream": "stream_pass"}[dom]
+    traffic = load_traffic(kname, args.config)
+
+    out_tol = {}
+    if not args.no_tol:
+        solver.reset()
+        solver.update_params(eps_abs=1e-4, max_iter=args.tol_max_iter)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r2 = solver.solve()
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        out_tol = {"time_to_tol_s": round(tt, 4), "iters_to_tol": int(r2["iterations"]),
+                   "tol_converged": bool(r2["converged"]), "eps_abs": 1e-4}
+        log(f"[bench] time to tol: {out_tol}")
+    solver.close()
+    del solver
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        k = args.cpu_iters
+        ro = oracle.run(inst32, k)
+        cpu = {"value": round(k / ro["loop_seconds"], 4), "unit": "iter/s",
+               "cores": ro["threads"], "kind": "oracle",
+               "sample": f"{k} iterations of the FP64 literal per-terminal oracle on the same "
+                         f"{args.config} instance (setup excluded, {ro['loop_seconds']:.1f} s)"}
+        log(f"[bench] cpu baseline: {cpu}")
+
+    line = {
+        "metric": METRIC, "value": round(ips, 3), "unit": "iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config} (m={inst.m}, n={inst.n}, nnz={inst.nnz})",
+                   "m": inst.m, "n": inst.n, "nnz": inst.nnz, "scale": args.scale,
+                   "route_len_mean": round(st["route_len_mean"], 4),
+                   "check_every": 10, "adapt_every": 50, "alpha": 1.6},
+        "model_gbs": round(bm["iteration"] * ips / 1e9, 2),
+        "model_bytes_per_iter": bm["iteration"],
+        "kernel_ms": {k2: round(v, 5) for k2, v in kt.items()},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": bm[dom]},
+        "cpu_baseline": cpu,
+        "setup_s": round(setup_s, 3),
+    }
+    line.update(out_tol)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

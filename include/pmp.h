@@ -171,6 +171,46 @@ pmp_status pmp_update_capacity(pmp_handle *h, const void *c_new);
 pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **b,
                             void **zs, void **v);
 
+/* Change eps_abs, mu, gamma and max_iter of an existing handle (alpha,
+ * check_every and adapt_every are fixed at setup: PMP_ERR_INVALID if they
+ * differ).  Synchronises the handle's stream. */
+pmp_status pmp_update_params(pmp_handle *h, const pmp_params *params);
+
+/* Residual history: up to `capacity` most recent checks, oldest first, as
+ * rows (iteration, ||r||, ||s||, rho) of 4 doubles in host memory `out`
+ * (the device keeps the last 4096).  *count receives the rows written. */
+pmp_status pmp_history(pmp_handle *h, double *out, int32_t capacity, int32_t *count);
+
+/* Measurement: run k iterations (same schedule as pmp_iterate) launching
+ * each pass on its own with HIP events around it on the handle's stream, and
+ * return average milliseconds in host ms[4]: plain stream pass, plain link
+ * pass, check stream pass, check link pass (0 when none ran). */
+pmp_status pmp_time_kernels(pmp_handle *h, int32_t k, double *ms);
+
+/* Replace the weights w[n] (device memory, problem dtype, > 0), keeping each
+ * stream's utility type and the iterate. */
+pmp_status pmp_update_weights(pmp_handle *h, const void *w_new);
+
+/* ---- reverse mode: gradients of K unrolled iterations ------------------
+ * J = sum_j U_j(x_j^K) for the rates x^K of the K-th iteration after the
+ * handle's current state, at the current rho (no balancing inside the K
+ * iterations).  Its gradients with respect to c and w approach the
+ * envelope values dU*/dc = lambda and dU*/dw_j = log x_j* (for log
+ * utilities) as K grows (the KKT relation of Section VI-B).
+ * The forward pass keeps the state every s iterations in `adj_workspace`
+ * (caller-owned device memory of pmp_adjoint_workspace_size bytes, 256-byte
+ * aligned, which must stay valid until pmp_backward); the backward pass
+ * recomputes each segment of s iterations, records x and the slack-prox mask,
+ * and runs the reverse iteration.  Afterwards the handle holds the state of
+ * iteration K again. */
+pmp_status pmp_adjoint_workspace_size(pmp_handle *h, int32_t K, int32_t s, size_t *bytes);
+/* Run K iterations with checkpoints every s; J (host) receives the objective. */
+pmp_status pmp_forward_ckpt(pmp_handle *h, int32_t K, int32_t s, void *adj_workspace,
+                            size_t adj_bytes, double *J);
+/* dJ/dc[m] and dJ/dw[n] into device buffers of the problem dtype (either may be
+ * NULL).  PMP_ERR_STATE without a preceding pmp_forward_ckpt. */
+pmp_status pmp_backward(pmp_handle *h, void *grad_c, void *grad_w);
+
 pmp_status pmp_destroy(pmp_handle *h);
 
 const char *pmp_status_string(pmp_status s);

@@ -62,7 +62,7 @@ def _load():
         lib = ctypes.CDLL(build())
         lib.orc_run.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)] + \
-            [ctypes.c_void_p] * 7 + [ctypes.POINTER(_Result)]
+            [ctypes.c_void_p] * 9 + [ctypes.POINTER(_Result)]
         for name in ("orc_prox_log", "orc_prox_linear"):
             f = getattr(lib, name)
             f.restype = ctypes.c_double
@@ -113,15 +113,19 @@ def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
     if history:
         hr, hs, hrho = (np.zeros(max(1, iters)) for _ in range(3))
     zw = ctypes.c_double(0.0)
+    secs = ctypes.c_double(0.0)
+    nthr = ctypes.c_int32(0)
     res = _Result()
+    vp = lambda o: ctypes.cast(ctypes.byref(o), ctypes.c_void_p)
     rc = lib.orc_run(ctypes.byref(prob), ctypes.byref(prm), _ptr(x), _ptr(lam),
-                     _ptr(slack), _ptr(hr), _ptr(hs), _ptr(hrho),
-                     ctypes.cast(ctypes.byref(zw), ctypes.c_void_p), ctypes.byref(res))
+                     _ptr(slack), _ptr(hr), _ptr(hs), _ptr(hrho), vp(zw), vp(secs),
+                     vp(nthr), ctypes.byref(res))
     if rc != 0:
         raise RuntimeError(f"orc_run failed with code {rc}")
     out = {"x": x, "lam": lam, "slack": slack, "iterations": int(res.iterations),
            "r_norm": res.r_norm, "s_norm": res.s_norm, "eps_tol": res.eps_tol,
-           "rho": res.rho, "converged": bool(res.converged), "zsum_worst": zw.value}
+           "rho": res.rho, "converged": bool(res.converged), "zsum_worst": zw.value,
+           "loop_seconds": secs.value, "threads": int(nthr.value)}
     if history:
         k = int(res.iterations)
         out.update(hist_r=hr[:k], hist_s=hs[:k], hist_rho=hrho[:k])

@@ -172,6 +172,8 @@ static void free_terminals(terminals *T)
  *   lambda[m]  link prices rho * u
  *   slack[m]   s = p_slack + c (eq. (4)'s recovery relation)
  *   hist_r, hist_s, hist_rho [max_iter]: per-iteration ||r||, ||s||, rho used
+ *   loop_seconds  wall time of the iteration loop (setup excluded)
+ *   threads_used  OpenMP threads of the parallel loops
  *   zsum_worst  max over iterations and links of |1^T z_l| / (1 + max|z_l|):
  *               the link flow-balance indicator g_l (Section III-C) asks
  *               1^T z_l = 0 after every z-update
@@ -180,7 +182,8 @@ static void free_terminals(terminals *T)
 int orc_run(const orc_problem *P, const orc_params *prm,
             double *x, double *lambda, double *slack,
             double *hist_r, double *hist_s, double *hist_rho,
-            double *zsum_worst, orc_result *res)
+            double *zsum_worst, double *loop_seconds, int32_t *threads_used,
+            orc_result *res)
 {
     if (prm->max_iter < 0 || prm->rho0 <= 0.0) return -2;
     if (prm->stop && prm->check_every <= 0) return -2;
@@ -213,6 +216,12 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     double r_norm = 0.0, s_norm = 0.0, zsum_max = 0.0;
     int converged = 0;
     int64_t k;
+#ifdef _OPENMP
+    if (threads_used) *threads_used = omp_get_max_threads();
+    double t_start = omp_get_wtime();
+#else
+    if (threads_used) *threads_used = 1;
+#endif
 
     for (k = 1; k <= prm->max_iter; ++k) {
         /* 1. proximal device updates: p_sigma = prox(z_sigma - u_sigma) */
@@ -298,6 +307,11 @@ int orc_run(const orc_problem *P, const orc_params *prm,
         }
     }
     if (k > prm->max_iter) k = prm->max_iter;
+#ifdef _OPENMP
+    if (loop_seconds) *loop_seconds = omp_get_wtime() - t_start;
+#else
+    if (loop_seconds) *loop_seconds = 0.0;
+#endif
 
     if (x) for (int64_t j = 0; j < n; ++j) x[j] = xs[j];
     if (lambda) for (int64_t l = 0; l < m; ++l) lambda[l] = rho * u[nnz + l];

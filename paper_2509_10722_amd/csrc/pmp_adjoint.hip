@@ -1,0 +1,325 @@
+// Reverse mode of K unrolled PMP iterations at fixed rho.
+//
+// The objective is J = sum_j U_j(x_j^K) (Section II's utilities at the rates
+// of the K-th iteration).  With A, B, Z, U the adjoints of the compact state
+// (a, b, zs, u) and mu_l = [zs_l - u_l > -c_l] the slack-prox mask, one
+// forward iteration t reverses as
+//   link step    pbb = alpha (U - B - Z);  psb = alpha Z + pbb / (d + 1)
+//                ybar = pbb / (d + 1);     cbar -= (1 - mu) psb
+//                B <- (1 - alpha) B;  Z <- (1 - alpha) Z + mu psb;
+//                U <- U - mu psb
+//   stream step  xbar = alpha A + R^T ybar (+ dJ/dx at t = K)
+//                Sbar = xbar dP/dS, wbar += xbar dP/dw when lo < x < hi
+//                A <- (1 - alpha) A + L Sbar
+//   link gather  vbar = R Sbar;  B <- B + vbar;  U <- U - vbar
+// where P is the log or linear prox of Section III-E.  For the log prox,
+// rho L x^2 - rho S x - w = 0 gives sqrt(S^2 + 4wL/rho) = L x + w/(rho x), so
+// dP/dS = rho x^2 / (rho L x^2 + w) and dP/dw = x / (rho L x^2 + w) follow
+// from the recorded rate alone; the linear prox has dP/dS = 1/L and
+// dP/dw = 1/(rho L).  The link gather of iteration t is fused with the link
+// step of iteration t - 1.
+#include "pmp_internal.h"
+
+#include <cmath>
+
+namespace pmp {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double *sh)
+{
+    v = wave_sum_d(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+// LDS-staged gather of a double vector over one workgroup's index range.
+__device__ __forceinline__ void gather_stage_d(const int *__restrict__ idx,
+                                               const double *__restrict__ tab, double *sh,
+                                               int cnt)
+{
+    constexpr int R = kCap / kBlock;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kBlock + threadIdx.x;
+        if (i < cnt) sh[i] = tab[__builtin_nontemporal_load(idx + i)];
+    }
+}
+
+__device__ __forceinline__ void link_step(const AdjDev &a, int l, int deg, double alpha,
+                                          uint8_t mu)
+{
+    const double B = a.B[l], Z = a.Z[l], U = a.U[l];
+    const double inv = 1.0 / ((double)deg + 1.0);
+    const double pbb = alpha * (U - B - Z);
+    const double psb = alpha * Z + pbb * inv;
+    const double m1 = mu ? 1.0 : 0.0;
+    a.ybar[l] = pbb * inv;
+    a.cbar[l] -= (1.0 - m1) * psb;
+    a.B[l] = (1.0 - alpha) * B;
+    a.Z[l] = (1.0 - alpha) * Z + m1 * psb;
+    a.U[l] = U - m1 * psb;
+}
+
+template <typename T>
+__device__ __forceinline__ void stream_step(const Dev<T> &d, const AdjDev &a, const T *xt,
+                                            int j, int L, double ysum, int last, double rho)
+{
+    double xbar = d.alpha * a.A[j] + ysum;
+    if (last) xbar += a.ext[j];
+    const double x = (double)xt[j];
+    const double wsig = (double)d.wsig[j];
+    double sbar = 0.0;
+    if (L > 0 && x > d.lo && x < d.hi) {
+        double dS, dw;
+        if (wsig > 0.0) {
+            const double den = rho * (double)L * x * x + wsig;
+            dS = rho * x * x / den;
+            dw = x / den;
+        } else {
+            dS = 1.0 / (double)L;
+            dw = 1.0 / (rho * (double)L);
+        }
+        sbar = xbar * dS;
+        a.wbar[j] += xbar * dw;
+    }
+    a.A[j] = (1.0 - d.alpha) * a.A[j] + (double)L * sbar;
+    a.Sbar[j] = sbar;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const T *xt, int last)
+{
+    __shared__ double sy[kCap];
+    __shared__ double sred[kBlock / 64];
+    const int blk = blockIdx.x;
+    const int s0 = d.sblk[blk], s1 = d.sblk[blk + 1];
+    const int e0 = d.col_ptr[s0];
+    const int cnt = d.col_ptr[s1] - e0;
+    const double rho = d.ctl->rho;
+    if (cnt <= kCap) {
+        gather_stage_d(d.row_idx + e0, a.ybar, sy, cnt);
+        __syncthreads();
+        const int j = s0 + (int)threadIdx.x;
+        if (j < s1) {
+            const int b = d.col_ptr[j] - e0, e = d.col_ptr[j + 1] - e0;
+            double acc = 0.0;
+            for (int k = b; k < e; ++k) acc += sy[k];
+            stream_step<T>(d, a, xt, j, e - b, acc, last, rho);
+        }
+    } else {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kBlock)
+            acc += a.ybar[__builtin_nontemporal_load(d.row_idx + e0 + k)];
+        acc = block_sum_d(acc, sred);
+        if (threadIdx.x == 0) stream_step<T>(d, a, xt, s0, cnt, acc, last, rho);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_link(Dev<T> d, AdjDev a, const uint8_t *mu_prev)
+{
+    __shared__ double ss[kCap];
+    __shared__ double sred[kBlock / 64];
+    const int blk = blockIdx.x;
+    const int l0 = d.lblk[blk], l1 = d.lblk[blk + 1];
+    const int e0 = d.row_ptr[l0];
+    const int cnt = d.row_ptr[l1] - e0;
+    int l = -1, deg = 0;
+    double acc = 0.0;
+    if (cnt <= kCap) {
+        gather_stage_d(d.col_idx + e0, a.Sbar, ss, cnt);
+        __syncthreads();
+        if (l0 + (int)threadIdx.x < l1) {
+            l = l0 + (int)threadIdx.x;
+            const int b = d.row_ptr[l] - e0, e = d.row_ptr[l + 1] - e0;
+            for (int k = b; k < e; ++k) acc += ss[k];
+            deg = e - b;
+        }
+    } else {
+        for (int k = threadIdx.x; k < cnt; k += kBlock)
+            acc += a.Sbar[__builtin_nontemporal_load(d.col_idx + e0 + k)];
+        acc = block_sum_d(acc, sred);
+        if (threadIdx.x == 0) {
+            l = l0;
+            deg = cnt;
+        }
+    }
+    if (l >= 0) {
+        a.B[l] += acc;
+        a.U[l] -= acc;
+        if (mu_prev) link_step(a, l, deg, d.alpha, mu_prev[l]);
+    }
+}
+
+template <typename T>
+__global__ void k_adj_link_only(Dev<T> d, AdjDev a, const uint8_t *mu)
+{
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += gridDim.x * blockDim.x)
+        link_step(a, l, d.row_ptr[l + 1] - d.row_ptr[l], d.alpha, mu[l]);
+}
+
+template <typename T>
+__global__ void k_slack_mask(Dev<T> d, uint8_t *mu)
+{
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += gridDim.x * blockDim.x)
+        mu[l] = ((double)d.zs[l] - (double)d.u[l]) > -(double)d.c[l] ? 1 : 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_objective(Dev<T> d, double *part)
+{
+    __shared__ double sred[kBlock / 64];
+    double acc = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
+        const double x = (double)d.x[j], ws = (double)d.wsig[j];
+        acc += ws > 0.0 ? ws * log(x) : -ws * x;
+    }
+    acc = block_sum_d(acc, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double *part, int count, double *out)
+{
+    __shared__ double sred[kBlock / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) acc += part[i];
+    acc = block_sum_d(acc, sred);
+    if (threadIdx.x == 0) *out = acc;
+}
+
+template <typename T>
+__global__ void k_adj_init(Dev<T> d, AdjDev a)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
+        const double x = (double)d.x[j], ws = (double)d.wsig[j];
+        // dJ/dw_j (direct) and dJ/dx_j^K
+        a.wbar[j] = ws > 0.0 ? log(x) : x;
+        a.ext[j] = ws > 0.0 ? ws / x : -ws;
+        a.A[j] = 0.0;
+        a.Sbar[j] = 0.0;
+    }
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
+        a.B[l] = 0.0;
+        a.Z[l] = 0.0;
+        a.U[l] = 0.0;
+        a.ybar[l] = 0.0;
+        a.cbar[l] = 0.0;
+    }
+}
+
+template <typename T>
+__global__ void k_adj_out(Dev<T> d, AdjDev a, T *gc, T *gw)
+{
+    const int stride = gridDim.x * blockDim.x;
+    if (gw)
+        for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride)
+            gw[j] = (T)a.wbar[j];
+    if (gc)
+        for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride)
+            gc[l] = (T)a.cbar[l];
+}
+
+template <typename T>
+__global__ void k_copy_weights(Dev<T> d, const T *w_new)
+{
+    unsigned f = 0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
+        const double w = (double)w_new[j];
+        if (!(w > 0.0) || !isfinite(w)) f |= kErrWeight;
+        T *ws = const_cast<T *>(d.wsig);
+        ws[j] = (double)ws[j] > 0.0 ? (T)w : (T)(-w);
+    }
+    if (f) atomicOr(&d.ctl->flags, f);
+}
+
+inline int grid_of(long long count, int cap = 16384)
+{
+    long long g = (count + kBlock - 1) / kBlock;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+template <typename T>
+void launch_adj_stream(const Dev<T> &d, const AdjDev &a, const T *xt, int last, hipStream_t s)
+{
+    if (d.nsb) hipLaunchKernelGGL((k_adj_stream<T>), dim3(d.nsb), dim3(kBlock), 0, s, d, a, xt, last);
+}
+
+template <typename T>
+void launch_adj_link(const Dev<T> &d, const AdjDev &a, const uint8_t *mu_prev, hipStream_t s)
+{
+    if (d.nlb) hipLaunchKernelGGL((k_adj_link<T>), dim3(d.nlb), dim3(kBlock), 0, s, d, a, mu_prev);
+}
+
+template <typename T>
+void launch_adj_link_only(const Dev<T> &d, const AdjDev &a, const uint8_t *mu, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_adj_link_only<T>), dim3(grid_of(d.m)), dim3(kBlock), 0, s, d, a, mu);
+}
+
+template <typename T>
+void launch_slack_mask(const Dev<T> &d, uint8_t *mu, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_slack_mask<T>), dim3(grid_of(d.m)), dim3(kBlock), 0, s, d, mu);
+}
+
+template <typename T>
+void launch_objective(const Dev<T> &d, double *part, int nblocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_objective<T>), dim3(nblocks), dim3(kBlock), 0, s, d, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, part, nblocks, out);
+}
+
+template <typename T>
+void launch_adj_init(const Dev<T> &d, const AdjDev &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_adj_init<T>), dim3(grid_of(d.n > d.m ? d.n : d.m)), dim3(kBlock), 0, s,
+                       d, a);
+}
+
+template <typename T>
+void launch_adj_out(const Dev<T> &d, const AdjDev &a, T *gc, T *gw, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_adj_out<T>), dim3(grid_of(d.n > d.m ? d.n : d.m)), dim3(kBlock), 0, s,
+                       d, a, gc, gw);
+}
+
+template <typename T>
+void launch_copy_weights(const Dev<T> &d, const T *w_new, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_copy_weights<T>), dim3(grid_of(d.n)), dim3(kBlock), 0, s, d, w_new);
+}
+
+#define PMP_ADJ_INSTANTIATE(T)                                                                \
+    template void launch_adj_stream<T>(const Dev<T> &, const AdjDev &, const T *, int,       \
+                                       hipStream_t);                                         \
+    template void launch_adj_link<T>(const Dev<T> &, const AdjDev &, const uint8_t *,        \
+                                     hipStream_t);                                           \
+    template void launch_adj_link_only<T>(const Dev<T> &, const AdjDev &, const uint8_t *,   \
+                                          hipStream_t);                                      \
+    template void launch_slack_mask<T>(const Dev<T> &, uint8_t *, hipStream_t);              \
+    template void launch_objective<T>(const Dev<T> &, double *, int, double *, hipStream_t); \
+    template void launch_adj_init<T>(const Dev<T> &, const AdjDev &, hipStream_t);           \
+    template void launch_adj_out<T>(const Dev<T> &, const AdjDev &, T *, T *, hipStream_t);  \
+    template void launch_copy_weights<T>(const Dev<T> &, const T *, hipStream_t);
+
+PMP_ADJ_INSTANTIATE(float)
+PMP_ADJ_INSTANTIATE(double)
+
+}  // namespace pmp

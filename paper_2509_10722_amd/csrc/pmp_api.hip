@@ -45,7 +45,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
-    size_t sblk, lblk, spart, lpart, ctl, hist, util, total;
+    size_t sblk, lblk, spart, lpart, sgpart, lgpart, scnt, lcnt, stotal, ctl, hist, util, total;
     int nsb_max, nlb_max;
 };
 
@@ -82,6 +82,12 @@ Layout plan(int m, int n, long long nnz, size_t sz)
     L.lblk = take(((size_t)L.nlb_max + 1) * 4);
     L.spart = take((size_t)L.nsb_max * 8);
     L.lpart = take((size_t)L.nlb_max * 16);
+    const size_t ngs = (size_t)L.nsb_max / kGroup + 1, ngl = (size_t)L.nlb_max / kGroup + 1;
+    L.sgpart = take(ngs * 8);
+    L.lgpart = take(ngl * 16);
+    L.scnt = take((ngs + 1) * 4);
+    L.lcnt = take((ngl + 1) * 4);
+    L.stotal = take(8);
     L.ctl = take(sizeof(Ctl));
     L.hist = take(sizeof(HistEntry) * kHist);
     L.util = take((size_t)n);
@@ -142,6 +148,11 @@ struct pmp_handle {
     long long iter_fin = 0;        // iteration of the last queued check
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // reverse mode (pmp_forward_ckpt / pmp_backward)
+    char *adj_ws = nullptr;
+    size_t adj_bytes = 0;
+    int adj_K = 0, adj_s = 0;
+    bool adj_ready = false;
 };
 
 namespace {
@@ -216,6 +227,11 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     d.lblk = (int *)(ws + L.lblk);
     d.spart = (double *)(ws + L.spart);
     d.lpart = (double *)(ws + L.lpart);
+    d.sgpart = (double *)(ws + L.sgpart);
+    d.lgpart = (double *)(ws + L.lgpart);
+    d.scnt = (unsigned *)(ws + L.scnt);
+    d.lcnt = (unsigned *)(ws + L.lcnt);
+    d.stotal = (double *)(ws + L.stotal);
     d.ctl = (Ctl *)(ws + L.ctl);
     d.hist = (HistEntry *)(ws + L.hist);
     d.lo = p->lo;
@@ -255,6 +271,9 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     launch_transpose(row_ptr, col_idx, m, n, nnz, col_ptr, row_idx, (int *)(ws + L.a), s);
     launch_check_routes(col_ptr, n, p->hi, d.ctl, s);
     launch_init_state<T>(d, c_src, w_src, u_src, s);
+    launch_fill_int((int *)d.scnt, 0, (L.lcnt - L.scnt) / 4, s);
+    launch_fill_int((int *)d.lcnt, 0, (L.stotal - L.lcnt) / 4, s);
+    launch_fill_int((int *)d.stotal, 0, 2, s);
     HIP_TRY(hipGetLastError());
 
     // Workgroup tables from the two pointer arrays.
@@ -377,6 +396,260 @@ pmp_status solve_impl(pmp_handle *h, pmp_result *out)
     }
     if (st == PMP_ERR_NUMERIC) return fail(st, "non-finite residual at iteration %lld", c.iter);
     return st;
+}
+
+}  // namespace
+
+namespace {
+
+// ---- reverse mode ----------------------------------------------------------
+
+struct AdjLayout {
+    size_t ckpt, final_state, xK, tape_x, tape_mu, A, Sbar, wbar, ext, B, Z, U, ybar, cbar;
+    size_t part, J, total, state;
+    int nck, nobj;
+};
+
+AdjLayout adj_plan(int m, int n, int K, int s, size_t sz)
+{
+    AdjLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    L.nck = (K + s - 1) / s;
+    L.nobj = (int)std::max<long long>(1, std::min<long long>(4096, ((long long)n + kBlock - 1) / kBlock));
+    L.state = ((size_t)n + 3 * (size_t)m) * sz;
+    L.ckpt = take((size_t)L.nck * L.state);
+    L.final_state = take(L.state);
+    L.xK = take((size_t)n * sz);
+    L.tape_x = take((size_t)s * n * sz);
+    L.tape_mu = take((size_t)s * m);
+    L.A = take((size_t)n * 8);
+    L.Sbar = take((size_t)n * 8);
+    L.wbar = take((size_t)n * 8);
+    L.ext = take((size_t)n * 8);
+    L.B = take((size_t)m * 8);
+    L.Z = take((size_t)m * 8);
+    L.U = take((size_t)m * 8);
+    L.ybar = take((size_t)m * 8);
+    L.cbar = take((size_t)m * 8);
+    L.part = take((size_t)L.nobj * 8);
+    L.J = take(8);
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+pmp_status copy_state(pmp_handle *h, char *dst, bool save)
+{
+    Dev<T> &d = dev_of<T>(h);
+    const size_t n = (size_t)h->n * sizeof(T), m = (size_t)h->m * sizeof(T);
+    void *parts[4] = {d.a, d.b, d.zs, d.u};
+    size_t sizes[4] = {n, m, m, m};
+    size_t off = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (sizes[i]) {
+            if (save) HIP_TRY(hipMemcpyAsync(dst + off, parts[i], sizes[i], hipMemcpyDeviceToDevice, h->stream));
+            else HIP_TRY(hipMemcpyAsync(parts[i], dst + off, sizes[i], hipMemcpyDeviceToDevice, h->stream));
+        }
+        off += sizes[i];
+    }
+    if (!save) launch_refresh_v<T>(d, h->stream);
+    return PMP_OK;
+}
+
+AdjDev adj_views(char *ws, const AdjLayout &L)
+{
+    AdjDev a;
+    a.A = (double *)(ws + L.A);
+    a.Sbar = (double *)(ws + L.Sbar);
+    a.wbar = (double *)(ws + L.wbar);
+    a.ext = (double *)(ws + L.ext);
+    a.B = (double *)(ws + L.B);
+    a.Z = (double *)(ws + L.Z);
+    a.U = (double *)(ws + L.U);
+    a.ybar = (double *)(ws + L.ybar);
+    a.cbar = (double *)(ws + L.cbar);
+    return a;
+}
+
+template <typename T>
+pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
+{
+    Dev<T> &d = dev_of<T>(h);
+    const AdjLayout L = adj_plan(h->m, h->n, K, s, sizeof(T));
+    hipStream_t st = h->stream;
+    pmp_status rc;
+    launch_ctl_clear_done(h->ctl, st);
+    for (int t = 1; t <= K; ++t) {
+        if ((t - 1) % s == 0)
+            if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)((t - 1) / s) * L.state, true)) != PMP_OK)
+                return rc;
+        launch_stream_pass<T>(d, false, st);
+        launch_link_pass<T>(d, kPlain, 0, 0, st);
+    }
+    h->iter_enq += K;
+    if ((rc = copy_state<T>(h, ws + L.final_state, true)) != PMP_OK) return rc;
+    if (h->n) HIP_TRY(hipMemcpyAsync(ws + L.xK, d.x, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    launch_objective<T>(d, (double *)(ws + L.part), L.nobj, (double *)(ws + L.J), st);
+    HIP_TRY(hipGetLastError());
+    double jv = 0.0;
+    HIP_TRY(hipMemcpyAsync(&jv, ws + L.J, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (J) *J = jv;
+    h->adj_ws = ws;
+    h->adj_K = K;
+    h->adj_s = s;
+    h->adj_ready = true;
+    return PMP_OK;
+}
+
+template <typename T>
+pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
+{
+    Dev<T> &d = dev_of<T>(h);
+    const int K = h->adj_K, s = h->adj_s;
+    char *ws = h->adj_ws;
+    const AdjLayout L = adj_plan(h->m, h->n, K, s, sizeof(T));
+    const AdjDev a = adj_views(ws, L);
+    hipStream_t st = h->stream;
+    pmp_status rc;
+    T *tape_x = (T *)(ws + L.tape_x);
+    uint8_t *tape_mu = (uint8_t *)(ws + L.tape_mu);
+    launch_ctl_clear_done(h->ctl, st);
+    // adjoint seeds from x^K
+    if (h->n) HIP_TRY(hipMemcpyAsync(d.x, ws + L.xK, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    launch_adj_init<T>(d, a, st);
+    for (int seg = L.nck - 1; seg >= 0; --seg) {
+        const int t0 = seg * s, t1 = std::min(t0 + s, K);
+        if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)seg * L.state, false)) != PMP_OK) return rc;
+        for (int t = t0 + 1; t <= t1; ++t) {            // recompute, recording x^t and mu^t
+            launch_stream_pass<T>(d, false, st);
+            if (h->n)
+                HIP_TRY(hipMemcpyAsync(tape_x + (size_t)(t - t0 - 1) * h->n, d.x,
+                                       (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+            launch_slack_mask<T>(d, tape_mu + (size_t)(t - t0 - 1) * h->m, st);
+            launch_link_pass<T>(d, kPlain, 0, 0, st);
+        }
+        if (t1 < K)   // link step of iteration t1, deferred from the later segment
+            launch_adj_link_only<T>(d, a, tape_mu + (size_t)(t1 - t0 - 1) * h->m, st);
+        for (int t = t1; t > t0; --t) {
+            launch_adj_stream<T>(d, a, tape_x + (size_t)(t - t0 - 1) * h->n, t == K, st);
+            const uint8_t *mu_prev = t - 1 > t0 ? tape_mu + (size_t)(t - 2 - t0) * h->m : nullptr;
+            launch_adj_link<T>(d, a, mu_prev, st);
+        }
+    }
+    launch_adj_out<T>(d, a, gc, gw, st);
+    if ((rc = copy_state<T>(h, ws + L.final_state, false)) != PMP_OK) return rc;
+    if (h->n) HIP_TRY(hipMemcpyAsync(d.x, ws + L.xK, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return PMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pmp_status pmp_adjoint_workspace_size(pmp_handle *h, int32_t K, int32_t s, size_t *bytes)
+{
+    if (!h || !bytes || K < 1 || s < 1) return fail(PMP_ERR_INVALID, "bad argument");
+    *bytes = adj_plan(h->m, h->n, K, s, h->dtype == PMP_F64 ? 8 : 4).total;
+    return PMP_OK;
+}
+
+pmp_status pmp_forward_ckpt(pmp_handle *h, int32_t K, int32_t s, void *adj_workspace,
+                            size_t adj_bytes, double *J)
+{
+    if (!h || K < 1 || s < 1) return fail(PMP_ERR_INVALID, "bad argument");
+    const size_t need = adj_plan(h->m, h->n, K, s, h->dtype == PMP_F64 ? 8 : 4).total;
+    if (!adj_workspace || adj_bytes < need)
+        return fail(PMP_ERR_SHAPE, "adjoint workspace of %zu bytes needed, %zu given", need, adj_bytes);
+    if ((uintptr_t)adj_workspace % kAlign) return fail(PMP_ERR_INVALID, "adjoint workspace must be 256-byte aligned");
+    h->adj_ready = false;
+    return h->dtype == PMP_F32 ? forward_ckpt_impl<float>(h, K, s, (char *)adj_workspace, J)
+                               : forward_ckpt_impl<double>(h, K, s, (char *)adj_workspace, J);
+}
+
+pmp_status pmp_backward(pmp_handle *h, void *grad_c, void *grad_w)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    if (!h->adj_ready) return fail(PMP_ERR_STATE, "pmp_backward needs a preceding pmp_forward_ckpt");
+    return h->dtype == PMP_F32 ? backward_impl<float>(h, (float *)grad_c, (float *)grad_w)
+                               : backward_impl<double>(h, (double *)grad_c, (double *)grad_w);
+}
+
+pmp_status pmp_update_weights(pmp_handle *h, const void *w_new)
+{
+    if (!h || (!w_new && h->n)) return fail(PMP_ERR_INVALID, "NULL argument");
+    if (h->n == 0) return PMP_OK;
+    launch_ctl_clear_done(h->ctl, h->stream);
+    if (h->dtype == PMP_F32) launch_copy_weights<float>(h->df, (const float *)w_new, h->stream);
+    else launch_copy_weights<double>(h->dd, (const double *)w_new, h->stream);
+    HIP_TRY(hipGetLastError());
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (c.flags & kErrWeight) return fail(PMP_ERR_INVALID, "weights must be finite and > 0");
+    return PMP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+pmp_status time_kernels_impl(pmp_handle *h, int k, double *ms)
+{
+    Dev<T> &d = dev_of<T>(h);
+    hipStream_t s = h->stream;
+    const int adapt = h->prm.adapt_every;
+    std::vector<hipEvent_t> ev(3 * (size_t)k, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(PMP_ERR_HIP, "hipEventCreate failed");
+        }
+    std::vector<int> is_check((size_t)k);
+    launch_ctl_clear_done(h->ctl, s);
+    for (int i = 1; i <= k; ++i) {
+        const long long it = h->iter_enq + 1;
+        const bool check = i == k || (adapt > 0 && it % adapt == 0);
+        const bool next_check = i < k && (i + 1 == k || (adapt > 0 && (it + 1) % adapt == 0));
+        is_check[i - 1] = check;
+        (void)hipEventRecord(ev[3 * (i - 1)], s);
+        launch_stream_pass<T>(d, check, s);
+        (void)hipEventRecord(ev[3 * (i - 1) + 1], s);
+        launch_link_pass<T>(d, check ? kCheck : (next_check ? kSave : kPlain), it - h->iter_fin,
+                            0, s);
+        (void)hipEventRecord(ev[3 * (i - 1) + 2], s);
+        if (check) {
+            h->iter_fin = it;
+            if (adapt > 0 && it % adapt == 0) launch_rescale<T>(d, s);
+        }
+        h->iter_enq = it;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    double acc[4] = {0, 0, 0, 0};
+    int cnt[4] = {0, 0, 0, 0};
+    for (int i = 0; e == hipSuccess && i < k; ++i) {
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]);
+        (void)hipEventElapsedTime(&b, ev[3 * i + 1], ev[3 * i + 2]);
+        const int off = is_check[i] ? 2 : 0;
+        acc[off] += a;
+        acc[off + 1] += b;
+        cnt[off] += 1;
+        cnt[off + 1] += 1;
+    }
+    for (auto &f : ev) (void)hipEventDestroy(f);
+    if (e != hipSuccess) return fail(PMP_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    for (int i = 0; i < 4; ++i) ms[i] = cnt[i] ? acc[i] / cnt[i] : 0.0;
+    return PMP_OK;
 }
 
 }  // namespace
@@ -560,6 +833,56 @@ pmp_status pmp_set_state(pmp_handle *h, const void *state)
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     h->iter_enq = h->iter_fin = it;
+    return PMP_OK;
+}
+
+pmp_status pmp_update_params(pmp_handle *h, const pmp_params *params)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "handle is NULL");
+    pmp_status st = check_params(params);
+    if (st != PMP_OK) return st;
+    if (params->alpha != h->prm.alpha || params->check_every != h->prm.check_every ||
+        params->adapt_every != h->prm.adapt_every)
+        return fail(PMP_ERR_INVALID, "alpha, check_every and adapt_every are fixed at setup");
+    h->prm.eps_abs = params->eps_abs;
+    h->prm.mu = params->mu;
+    h->prm.gamma = params->gamma;
+    h->prm.max_iter = params->max_iter;
+    const double J = (double)h->nnz + (double)h->m;
+    launch_ctl_set_tolerances(h->ctl, params->eps_abs * std::sqrt(J), params->mu, params->gamma,
+                              h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PMP_OK;
+}
+
+pmp_status pmp_time_kernels(pmp_handle *h, int32_t k, double *ms)
+{
+    if (!h || !ms || k < 1) return fail(PMP_ERR_INVALID, "bad argument");
+    return h->dtype == PMP_F32 ? time_kernels_impl<float>(h, k, ms)
+                               : time_kernels_impl<double>(h, k, ms);
+}
+
+pmp_status pmp_history(pmp_handle *h, double *out, int32_t capacity, int32_t *count)
+{
+    if (!h || !count || capacity < 0 || (capacity > 0 && !out))
+        return fail(PMP_ERR_INVALID, "bad argument");
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const long long avail = std::min<long long>(c.nhist, kHist);
+    const int take = (int)std::min<long long>(avail, capacity);
+    std::vector<HistEntry> buf((size_t)kHist);
+    const HistEntry *dh = h->dtype == PMP_F32 ? h->df.hist : h->dd.hist;
+    HIP_TRY(hipMemcpy(buf.data(), dh, sizeof(HistEntry) * kHist, hipMemcpyDeviceToHost));
+    for (int i = 0; i < take; ++i) {        // oldest retained entry first
+        const long long idx = (c.nhist - take + i) % kHist;
+        out[4 * i] = (double)buf[(size_t)idx].iter;
+        out[4 * i + 1] = buf[(size_t)idx].r_norm;
+        out[4 * i + 2] = buf[(size_t)idx].s_norm;
+        out[4 * i + 3] = buf[(size_t)idx].rho;
+    }
+    *count = take;
     return PMP_OK;
 }
 

@@ -18,6 +18,9 @@ constexpr int kBlock = 256;
 constexpr int kCap = 4096;
 // Device history ring of (iteration, ||r||, ||s||, rho), one entry per check.
 constexpr int kHist = 4096;
+// Residual partials are reduced in two levels: groups of kGroup workgroups,
+// then the group sums; the last arrival at each level does the adding.
+constexpr int kGroup = 256;
 
 // Device-resident control block.  Kernels read rho and the done flag from
 // here, so a captured graph stays valid while rho changes (Section III-G
@@ -78,9 +81,25 @@ struct Dev {
     int nsb, nlb;
     double *spart;                  // [nsb]   stream residual partials
     double *lpart;                  // [2 nlb] link residual partials
+    double *sgpart;                 // [ceil(nsb/256)]     group sums
+    double *lgpart;                 // [2 ceil(nlb/256)]   group sums
+    unsigned *scnt;                 // [ceil(nsb/256) + 1] arrival counters
+    unsigned *lcnt;                 // [ceil(nlb/256) + 1] arrival counters
+    double *stotal;                 // stream part of ||s||^2 / rho^2
     double lo, hi, alpha;
     Ctl *ctl;
     HistEntry *hist;
+};
+
+// Adjoint (reverse-mode) vectors, all FP64, in the adjoint workspace.
+struct AdjDev {
+    double *A;       // [n] adjoint of a
+    double *Sbar;    // [n] adjoint of S of the current reverse iteration
+    double *wbar;    // [n] dJ/dw accumulator
+    double *ext;     // [n] dJ/dx^K
+    double *B, *Z, *U;   // [m] adjoints of b, zs, u
+    double *ybar;    // [m] adjoint of the link sums y
+    double *cbar;    // [m] dJ/dc accumulator
 };
 
 // Launchers (pmp_kernels.hip).
@@ -103,6 +122,24 @@ void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s);
 template <typename T>
 void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s);
 
+// Adjoint launchers (pmp_adjoint.hip).
+template <typename T>
+void launch_adj_stream(const Dev<T> &d, const AdjDev &a, const T *xt, int last, hipStream_t s);
+template <typename T>
+void launch_adj_link(const Dev<T> &d, const AdjDev &a, const uint8_t *mu_prev, hipStream_t s);
+template <typename T>
+void launch_adj_link_only(const Dev<T> &d, const AdjDev &a, const uint8_t *mu, hipStream_t s);
+template <typename T>
+void launch_slack_mask(const Dev<T> &d, uint8_t *mu, hipStream_t s);
+template <typename T>
+void launch_objective(const Dev<T> &d, double *part, int nblocks, double *out, hipStream_t s);
+template <typename T>
+void launch_adj_init(const Dev<T> &d, const AdjDev &a, hipStream_t s);
+template <typename T>
+void launch_adj_out(const Dev<T> &d, const AdjDev &a, T *gc, T *gw, hipStream_t s);
+template <typename T>
+void launch_copy_weights(const Dev<T> &d, const T *w_new, hipStream_t s);
+
 void launch_validate_csr(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
                          Ctl *ctl, hipStream_t s);
 // CSR -> CSC transpose of the pattern; `tmp` holds n + 1 + scan scratch ints.
@@ -113,6 +150,7 @@ void launch_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl, hipStre
 void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gamma,
                      int adapt_every, hipStream_t s);
 void launch_ctl_clear_done(Ctl *ctl, hipStream_t s);
+void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double mu, double gamma, hipStream_t s);
 void launch_fill_int(int *p, int value, size_t count, hipStream_t s);
 
 }  // namespace pmp

@@ -45,6 +45,53 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return r;
 }
 
+// Two-level arrival reduction of W doubles per workgroup.  Thread 0's v[] is
+// this workgroup's partial.  The last workgroup to arrive in a group of
+// kGroup adds the group's partials (in workgroup order), and the last group
+// to finish adds the group sums (in group order), so the total does not
+// depend on scheduling.  Returns true in that final workgroup, with the
+// totals in tot[] (thread 0).  Counters are left at zero.
+template <int W>
+__device__ bool reduce_arrive(const double (&v)[W], double *part, double *gpart, unsigned *cnt,
+                              int nblk, double *sred, double (&tot)[W])
+{
+    __shared__ int s_flag;
+    const int blk = blockIdx.x, g = blk / kGroup;
+    const int ng = (nblk + kGroup - 1) / kGroup;
+    const int gsize = min(kGroup, nblk - g * kGroup);
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < W; ++w) part[W * blk + w] = v[w];
+        __threadfence();
+        const unsigned prev = atomicAdd(&cnt[g], 1u);
+        s_flag = prev == (unsigned)gsize - 1u;
+    }
+    __syncthreads();
+    if (!s_flag) return false;
+    __threadfence();
+    double gs[W];
+    for (int w = 0; w < W; ++w) {
+        const double x = (int)threadIdx.x < gsize ? part[W * (g * kGroup + threadIdx.x) + w] : 0.0;
+        gs[w] = block_sum(x, sred);
+    }
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < W; ++w) gpart[W * g + w] = gs[w];
+        cnt[g] = 0u;
+        __threadfence();
+        const unsigned prev = atomicAdd(&cnt[ng], 1u);
+        s_flag = prev == (unsigned)ng - 1u;
+    }
+    __syncthreads();
+    if (!s_flag) return false;
+    __threadfence();
+    for (int w = 0; w < W; ++w) {
+        double x = 0.0;
+        for (int i = threadIdx.x; i < ng; i += kBlock) x += gpart[W * i + w];
+        tot[w] = block_sum(x, sred);
+    }
+    if (threadIdx.x == 0) cnt[ng] = 0u;
+    return true;
+}
+
 // Stage tab[idx[i]] for i < cnt into LDS.  Every lane first loads its share of
 // the index stream, then issues all of its gathers, then writes LDS, so up to
 // kCap / kBlock gathers per lane are in flight together.
@@ -172,26 +219,21 @@ __global__ __launch_bounds__(kBlock) void k_stream_pass(Dev<T> d)
         if (threadIdx.x == 0) part = stream_update<T, CHECK>(d, s0, cnt, acc, rho);
     }
     if (CHECK) {
-        part = block_sum(part, sred);
-        if (threadIdx.x == 0) d.spart[blk] = part;
+        const double v[1] = {block_sum(part, sred)};
+        double tot[1];
+        if (reduce_arrive<1>(v, d.spart, d.sgpart, d.scnt, d.nsb, sred, tot) && threadIdx.x == 0)
+            *d.stotal = tot[0];
     }
 }
 
 // ---- residual reduction, stop rule and rho balancing ---------------------
 
+// Thread 0 of the last link workgroup: residual norms (Section III-F), the
+// stop rule, and residual balancing of rho (Section III-G).
 template <typename T>
-__device__ void finalize(const Dev<T> &d, long long delta, int stop, double *sred)
+__device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, double ss)
 {
-    __threadfence();
-    double sr = 0.0, ss = 0.0;
-    for (int i = threadIdx.x; i < d.nlb; i += kBlock) {
-        sr += d.lpart[2 * i];
-        ss += d.lpart[2 * i + 1];
-    }
-    for (int i = threadIdx.x; i < d.nsb; i += kBlock) ss += d.spart[i];
-    sr = block_sum(sr, sred);
-    ss = block_sum(ss, sred);
-    if (threadIdx.x != 0) return;
+    ss += *d.stotal;
     Ctl *c = d.ctl;
     const double rho = c->rho;
     const long long it = c->iter + delta;
@@ -220,7 +262,6 @@ __device__ void finalize(const Dev<T> &d, long long delta, int stop, double *sre
         c->ratio = rho / rn;
         c->rho = rn;
     }
-    c->arrive = 0u;
 }
 
 // ---- link pass -------------------------------------------------------------
@@ -231,7 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d, long long delta,
     if (d.ctl->done) return;
     __shared__ T sx[kCap];
     __shared__ double sred[kBlock / 64];
-    __shared__ int s_last;
     const int blk = blockIdx.x;
     const int l0 = d.lblk[blk], l1 = d.lblk[blk + 1];
     const int e0 = d.row_ptr[l0];
@@ -255,17 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d, long long delta,
         if (threadIdx.x == 0) link_update<T, MODE>(d, l0, cnt, acc, r2, s2);
     }
     if (MODE == kCheck) {
-        r2 = block_sum(r2, sred);
-        s2 = block_sum(s2, sred);
-        if (threadIdx.x == 0) {
-            d.lpart[2 * blk] = r2;
-            d.lpart[2 * blk + 1] = s2;
-            __threadfence();
-            const unsigned prev = atomicAdd(&d.ctl->arrive, 1u);
-            s_last = prev == gridDim.x - 1;
-        }
-        __syncthreads();
-        if (s_last) finalize<T>(d, delta, stop, sred);
+        const double v[2] = {block_sum(r2, sred), block_sum(s2, sred)};
+        double tot[2];
+        if (reduce_arrive<2>(v, d.lpart, d.lgpart, d.lcnt, d.nlb, sred, tot) && threadIdx.x == 0)
+            finalize<T>(d, delta, stop, tot[0], tot[1]);
     }
 }
 
@@ -498,6 +531,13 @@ __global__ void k_ctl_init(Ctl *c, double rho, double eps_tol, double mu, double
     c->flags = 0u;
 }
 
+__global__ void k_ctl_set_tolerances(Ctl *c, double eps_tol, double mu, double gamma)
+{
+    c->eps_tol = eps_tol;
+    c->mu = mu;
+    c->gamma = gamma;
+}
+
 __global__ void k_ctl_clear_done(Ctl *c)
 {
     c->done = 0;
@@ -660,6 +700,11 @@ void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gam
 {
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, ctl, rho, eps_tol, mu, gamma,
                        adapt_every);
+}
+
+void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double mu, double gamma, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_set_tolerances, dim3(1), dim3(1), 0, s, ctl, eps_tol, mu, gamma);
 }
 
 void launch_ctl_clear_done(Ctl *ctl, hipStream_t s)

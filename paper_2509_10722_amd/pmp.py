@@ -67,6 +67,15 @@ _SIGNATURES = {
     "pmp_set_state": [_P, _P],
     "pmp_update_capacity": [_P, _P],
     "pmp_device_views": [_P] + [ctypes.POINTER(_P)] * 6,
+    "pmp_update_params": [_P, ctypes.POINTER(pmp_params)],
+    "pmp_history": [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "pmp_time_kernels": [_P, ctypes.c_int32, _P],
+    "pmp_update_weights": [_P, _P],
+    "pmp_adjoint_workspace_size": [_P, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_size_t)],
+    "pmp_forward_ckpt": [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t,
+                         ctypes.POINTER(ctypes.c_double)],
+    "pmp_backward": [_P, _P, _P],
     "pmp_destroy": [_P],
 }
 
@@ -213,6 +222,55 @@ class Solver:
         c = self.torch.as_tensor(c_new).to(dtype=self.dtype, device=self.device).contiguous()
         _check(self.lib.pmp_update_capacity(self.handle, c.data_ptr()), "pmp_update_capacity")
 
+    def update_params(self, **kw):
+        for k, v in kw.items():
+            setattr(self.params, k, v)
+        _check(self.lib.pmp_update_params(self.handle, ctypes.byref(self.params)),
+               "pmp_update_params")
+
+    def history(self, capacity=4096):
+        out = np.zeros((capacity, 4))
+        cnt = ctypes.c_int32()
+        _check(self.lib.pmp_history(self.handle, out.ctypes.data, capacity, ctypes.byref(cnt)),
+               "pmp_history")
+        return out[: cnt.value]
+
+    def time_kernels(self, k):
+        ms = np.zeros(4)
+        _check(self.lib.pmp_time_kernels(self.handle, int(k), ms.ctypes.data), "pmp_time_kernels")
+        return {"stream": ms[0], "link": ms[1], "stream_check": ms[2], "link_check": ms[3]}
+
+    def reset(self):
+        """Back to the all-zero start with rho = rho0 (a fresh solve)."""
+        buf = self.torch.zeros(self.state_size(), dtype=self.torch.uint8, device=self.device)
+        tail = np.zeros(2, dtype=np.float64)
+        tail[0] = self.params.rho0
+        buf[-16:-8] = self.torch.from_numpy(tail[:1].view(np.uint8).copy()).to(self.device)
+        self.set_state(buf)
+
+    def update_weights(self, w_new):
+        w = self.torch.as_tensor(w_new).to(dtype=self.dtype, device=self.device).contiguous()
+        _check(self.lib.pmp_update_weights(self.handle, w.data_ptr()), "pmp_update_weights")
+
+    def forward_ckpt(self, K, s):
+        """K iterations from the current state with checkpoints every s;
+        returns J = sum_j U_j(x_j^K)."""
+        b = ctypes.c_size_t()
+        _check(self.lib.pmp_adjoint_workspace_size(self.handle, int(K), int(s), ctypes.byref(b)),
+               "pmp_adjoint_workspace_size")
+        self.adj_ws = self.torch.empty(b.value, dtype=self.torch.uint8, device=self.device)
+        J = ctypes.c_double()
+        _check(self.lib.pmp_forward_ckpt(self.handle, int(K), int(s), self.adj_ws.data_ptr(),
+                                         b.value, ctypes.byref(J)), "pmp_forward_ckpt")
+        return J.value
+
+    def backward(self):
+        """(dJ/dc, dJ/dw) of the last forward_ckpt."""
+        gc = self.torch.empty(self.m, dtype=self.dtype, device=self.device)
+        gw = self.torch.empty(max(self.n, 1), dtype=self.dtype, device=self.device)
+        _check(self.lib.pmp_backward(self.handle, gc.data_ptr(), gw.data_ptr()), "pmp_backward")
+        return gc, gw[: self.n]
+
     def views(self):
         """Zero-copy tensors over the internal x, u, a, b, zs, v."""
         ptrs = [ctypes.c_void_p() for _ in range(6)]
@@ -246,3 +304,40 @@ def _tensor_from_ptr(torch, ptr, count, dtype, device, workspace, esz):
     if off < 0 or off + count * esz > workspace.numel():
         raise ValueError("pointer outside the workspace")
     return workspace[off: off + count * esz].view(dtype)
+
+
+def _autograd_function():
+    import torch
+
+    class PMPFunction(torch.autograd.Function):
+        """J(c, w) = sum_j U_j(x_j^K) after K PMP iterations from the all-zero
+        start, with a hand-written reverse pass (pmp_backward) behind autograd.
+        Inputs c [m] and w [n] are device tensors of the solver's dtype."""
+
+        @staticmethod
+        def forward(ctx, c, w, solver, K, s):
+            solver.update_capacity(c.detach())
+            solver.update_weights(w.detach())
+            solver.reset()
+            J = solver.forward_ckpt(K, s)
+            ctx.solver = solver
+            return torch.tensor(J, dtype=torch.float64, device=c.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            gc, gw = ctx.solver.backward()
+            g = gJ.to(gc.dtype)
+            return g * gc, g * gw, None, None, None
+
+    return PMPFunction
+
+
+_PMPFunction = None
+
+
+def pmp_objective(c, w, solver, K, s=25):
+    """Differentiable J(c, w) (see PMPFunction)."""
+    global _PMPFunction
+    if _PMPFunction is None:
+        _PMPFunction = _autograd_function()
+    return _PMPFunction.apply(c, w, solver, K, s)

@@ -49,8 +49,10 @@ def test_tiny_fp64_equal_iterations(adapt):
     assert rel(g["x"], o["x"]) <= F64_TOL
     assert rel(g["lam"], o["lam"]) <= F64_TOL
     assert rel(g["slack"], o["slack"]) <= F64_TOL
-    assert abs(g["r"] - o["r_norm"]) <= 1e-8 * max(o["r_norm"], 1e-12)
-    assert abs(g["s"] - o["s_norm"]) <= 1e-6 * max(o["s_norm"], 1e-12)
+    # residual norms: the link averages cancel (y ~ -ps) near convergence, so
+    # allow a few ulps of the terms on top of the relative part
+    assert abs(g["r"] - o["r_norm"]) <= 1e-6 * o["r_norm"] + 1e-13
+    assert abs(g["s"] - o["s_norm"]) <= 1e-6 * o["s_norm"] + 1e-13
 
 
 def test_tiny_fp32_equal_iterations():
@@ -140,8 +142,25 @@ def test_solve_matches_oracle_stop(dtype_name):
         assert rel(host(x), o["x"]) <= F64_TOL
     else:
         assert abs(res["iterations"] - o["iterations"]) <= 20
+
+
+@pytest.mark.parametrize("dtype_name,eps,tol", [("float64", 1e-9, 1e-6), ("float32", 1e-6, 1e-3)])
+def test_tight_solve_is_kkt_point(dtype_name, eps, tol):
+    """The stop rule's absolute tolerance eps_abs sqrt(J) is loose at 1e-4;
+    solved tighter, the rates and prices satisfy the optimality conditions
+    (Section VI-B's w/x = R^T lambda among them)."""
+    dtype = getattr(torch, dtype_name)
+    inst = I.tiny() if dtype_name == "float64" else I.tiny().rounded(np.float32)
+    s = Solver(inst, dtype=dtype, eps_abs=eps, max_iter=200000)
+    res = s.solve()
+    x, lam, _ = s.solution()
+    s.close()
+    assert res["converged"]
     rep = opt.kkt_report(inst, host(x), host(lam))
-    assert rep["primal_infeas"] < 1e-2 and rep["rel_gap"] < 1e-2
+    print(dtype_name, rep)
+    assert rep["primal_infeas"] < tol and rep["dual_infeas"] < tol
+    assert rep["comp_slack"] < tol and rep["stationarity_log"] < 10 * tol
+    assert -tol <= rep["rel_gap"] < tol
 
 
 def test_zsum_invariant_compact_form():
@@ -205,7 +224,7 @@ def test_capacity_degradation_warm_start():
     inst = I.tiny()
     rng = np.random.default_rng(5)
     c_new = inst.c * np.where(rng.random(inst.m) < 0.25, 0.5, 1.0)
-    warm = Solver(inst, dtype=torch.float64)
+    warm = Solver(inst, dtype=torch.float64, eps_abs=1e-8, max_iter=200000)
     assert warm.solve()["converged"]
     warm.update_capacity(c_new)
     rw = warm.solve()
@@ -213,13 +232,14 @@ def test_capacity_degradation_warm_start():
     warm.close()
     deg = I.Instance(inst.name, inst.m, inst.n, inst.row_ptr, inst.col_idx, c_new, inst.w,
                      inst.utility, inst.lo, inst.hi)
-    cold = Solver(deg, dtype=torch.float64)
+    cold = Solver(deg, dtype=torch.float64, eps_abs=1e-8, max_iter=200000)
     rc = cold.solve()
     cold.close()
     assert rw["converged"] and rc["converged"]
     assert rw["iterations"] < rc["iterations"]
+    print(f"degradation re-solve: warm {rw['iterations']} it, cold {rc['iterations']} it")
     rep = opt.kkt_report(deg, host(xw), host(lw))
-    assert rep["primal_infeas"] < 1e-2 and rep["rel_gap"] < 1e-2
+    assert rep["primal_infeas"] < 1e-5 and abs(rep["rel_gap"]) < 1e-5
 
 
 @pytest.mark.parametrize("mutate,text", [
