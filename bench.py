@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--no-tol", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--layout", default="auto", choices=["auto", "gather", "binned"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (known bytes) for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -86,6 +89,16 @@ def main():
         sys.exit(1)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
 
+    if args.calibrate_copy:
+        # an elementwise kernel that reads and writes 1 GiB each (known bytes)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration: 3 x torch.mul over {src.numel() * 4} bytes in and out")
+        del src, dst
+
     t0 = time.perf_counter()
     inst = instances.make(args.config, scale=args.scale)
     gen_s = time.perf_counter() - t0
@@ -95,7 +108,10 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solver = Solver(inst32, dtype=torch.float32, eps_abs=0.0, max_iter=max(1, args.warmup))
+    layout = {"auto": 0, "gather": 1, "binned": 2}[args.layout]
+    solver = Solver(inst32, dtype=torch.float32, eps_abs=0.0, max_iter=max(1, args.warmup),
+                    layout=layout)
+    used = solver.layout_in_use()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.2f} s")
@@ -155,7 +171,7 @@ def main():
         "config": {"workload": f"{args.config} (m={inst.m}, n={inst.n}, nnz={inst.nnz})",
                    "m": inst.m, "n": inst.n, "nnz": inst.nnz, "scale": args.scale,
                    "route_len_mean": round(st["route_len_mean"], 4),
-                   "check_every": 10, "adapt_every": 50, "alpha": 1.6},
+                   "check_every": 10, "adapt_every": 50, "alpha": 1.6, "layout": used},
         "model_gbs": round(bm["iteration"] * ips / 1e9, 2),
         "model_bytes_per_iter": bm["iteration"],
         "kernel_ms": {k2: round(v, 5) for k2, v in kt.items()},

@@ -98,10 +98,19 @@ typedef struct {
  *   adapt_every  rho balancing period in iterations (0 = fixed rho); must be
  *                a multiple of check_every
  *   check_every  residual / stop-test period of pmp_solve (>= 1)
- *   max_iter     iteration cap of one pmp_solve call */
+ *   max_iter     iteration cap of one pmp_solve call
+ *   layout       sparse layout of the iteration: PMP_LAYOUT_AUTO picks
+ *                PMP_LAYOUT_BINNED for FP32 problems with nnz >= 2^24 and
+ *                PMP_LAYOUT_GATHER otherwise.  GATHER: CSR / CSC passes with
+ *                LDS-staged gathers.  BINNED: R tiled into link-block x
+ *                stream-block tiles with one FP32 message per nonzero per
+ *                direction, streamed through HBM in coalesced runs (for
+ *                large unstructured R, where random gathers are slow). */
+typedef enum { PMP_LAYOUT_AUTO = 0, PMP_LAYOUT_GATHER = 1, PMP_LAYOUT_BINNED = 2 } pmp_layout;
 typedef struct {
     double rho0, alpha, mu, gamma, eps_abs;
     int32_t adapt_every, check_every, max_iter;
+    int32_t layout;
 } pmp_params;
 
 typedef struct {
@@ -116,10 +125,11 @@ typedef struct {
 typedef struct pmp_handle pmp_handle;
 
 /* Defaults: rho0 1, alpha 1.6, mu 2, gamma 1.1, eps_abs 1e-4, adapt_every 50,
- * check_every 10, max_iter 100000 (Section III-G's constants). */
+ * check_every 10, max_iter 100000 (Section III-G's constants), layout AUTO. */
 pmp_status pmp_params_default(pmp_params *params);
 
-/* Workspace bytes needed for `problem` (reads only m, n, nnz, dtype). */
+/* Workspace bytes needed for `problem` (reads only m, n, nnz, dtype) with
+ * the layout `params` selects. */
 pmp_status pmp_workspace_size(const pmp_problem *problem, const pmp_params *params,
                               size_t *bytes);
 
@@ -194,9 +204,10 @@ pmp_status pmp_update_weights(pmp_handle *h, const void *w_new);
 /* ---- reverse mode: gradients of K unrolled iterations ------------------
  * J = sum_j U_j(x_j^K) for the rates x^K of the K-th iteration after the
  * handle's current state, at the current rho (no balancing inside the K
- * iterations).  Its gradients with respect to c and w approach the
- * envelope values dU*/dc = lambda and dU*/dw_j = log x_j* (for log
- * utilities) as K grows (the KKT relation of Section VI-B).
+ * iterations).  As K grows its gradients approach the envelope values of
+ * the optimal utility U_opt: dU_opt/dc_l = lambda_l and
+ * dU_opt/dw_j = log x_j (log utilities), from the KKT relation of
+ * Section VI-B.
  * The forward pass keeps the state every s iterations in `adj_workspace`
  * (caller-owned device memory of pmp_adjoint_workspace_size bytes, 256-byte
  * aligned, which must stay valid until pmp_backward); the backward pass
@@ -210,6 +221,9 @@ pmp_status pmp_forward_ckpt(pmp_handle *h, int32_t K, int32_t s, void *adj_works
 /* dJ/dc[m] and dJ/dw[n] into device buffers of the problem dtype (either may be
  * NULL).  PMP_ERR_STATE without a preceding pmp_forward_ckpt. */
 pmp_status pmp_backward(pmp_handle *h, void *grad_c, void *grad_w);
+
+/* The layout chosen at setup (PMP_LAYOUT_GATHER or PMP_LAYOUT_BINNED). */
+pmp_status pmp_get_layout(pmp_handle *h, int32_t *layout);
 
 pmp_status pmp_destroy(pmp_handle *h);
 

@@ -44,12 +44,22 @@ constexpr int kSlots = 4;   // pipelined chunks in flight in pmp_solve
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
+    size_t mx, mv, lix, six, ox, ov;
+    bool binned;
+    BinnedPlan bp;
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
-    size_t sblk, lblk, spart, lpart, sgpart, lgpart, scnt, lcnt, stotal, ctl, hist, util, total;
+    size_t sblk, lblk, spart, lpart, ctl, hist, util, total;
     int nsb_max, nlb_max;
 };
 
-Layout plan(int m, int n, long long nnz, size_t sz)
+bool use_binned(int m, int n, long long nnz, size_t sz, int layout)
+{
+    if (layout == PMP_LAYOUT_BINNED) return m > 0 && n > 0;
+    if (layout == PMP_LAYOUT_GATHER) return false;
+    return sz == 4 && nnz >= (1LL << 24) && m >= 256 && n >= 256;
+}
+
+Layout plan(int m, int n, long long nnz, size_t sz, int layout)
 {
     Layout L{};
     size_t off = 0;
@@ -62,6 +72,12 @@ Layout plan(int m, int n, long long nnz, size_t sz)
     // consecutive blocks hold more than kCap nonzeros.
     L.nsb_max = (int)std::min<long long>((long long)n, n / kBlock + 2 * nnz / kCap + 2);
     L.nlb_max = (int)std::min<long long>((long long)m, m / kBlock + 2 * nnz / kCap + 2);
+    L.binned = use_binned(m, n, nnz, sz, layout);
+    if (L.binned) {
+        L.bp = binned_plan(m, n);
+        L.nsb_max = std::max(L.nsb_max, L.bp.Q);
+        L.nlb_max = std::max(L.nlb_max, L.bp.P);
+    }
     L.row_ptr = take(((size_t)m + 1) * 4);
     L.col_idx = take((size_t)nnz * 4);
     L.col_ptr = take(((size_t)n + 1) * 4);
@@ -82,15 +98,18 @@ Layout plan(int m, int n, long long nnz, size_t sz)
     L.lblk = take(((size_t)L.nlb_max + 1) * 4);
     L.spart = take((size_t)L.nsb_max * 8);
     L.lpart = take((size_t)L.nlb_max * 16);
-    const size_t ngs = (size_t)L.nsb_max / kGroup + 1, ngl = (size_t)L.nlb_max / kGroup + 1;
-    L.sgpart = take(ngs * 8);
-    L.lgpart = take(ngl * 16);
-    L.scnt = take((ngs + 1) * 4);
-    L.lcnt = take((ngl + 1) * 4);
-    L.stotal = take(8);
     L.ctl = take(sizeof(Ctl));
     L.hist = take(sizeof(HistEntry) * kHist);
     L.util = take((size_t)n);
+    if (L.binned) {
+        const size_t tiles = (size_t)L.bp.P * (size_t)L.bp.Q + 1;
+        L.mx = take((size_t)nnz * sz);
+        L.mv = take((size_t)nnz * sz);
+        L.lix = take((size_t)nnz * 2);
+        L.six = take((size_t)nnz * 2);
+        L.ox = take(tiles * 8);
+        L.ov = take(tiles * 8);
+    }
     L.total = off;
     return L;
 }
@@ -175,6 +194,8 @@ pmp_status check_params(const pmp_params *p)
     if (p->adapt_every < 0 || (p->adapt_every > 0 && p->adapt_every % p->check_every != 0))
         return fail(PMP_ERR_INVALID, "adapt_every must be 0 or a multiple of check_every");
     if (p->max_iter < 0) return fail(PMP_ERR_INVALID, "max_iter must be >= 0");
+    if (p->layout < PMP_LAYOUT_AUTO || p->layout > PMP_LAYOUT_BINNED)
+        return fail(PMP_ERR_INVALID, "unknown layout");
     return PMP_OK;
 }
 
@@ -199,7 +220,7 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
 {
     const int m = p->m, n = p->n;
     const long long nnz = p->nnz;
-    const Layout L = plan(m, n, nnz, sizeof(T));
+    const Layout L = plan(m, n, nnz, sizeof(T), h->prm.layout);
     hipStream_t s = h->stream;
     Dev<T> &d = dev_of<T>(h);
     d.m = m;
@@ -227,11 +248,6 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     d.lblk = (int *)(ws + L.lblk);
     d.spart = (double *)(ws + L.spart);
     d.lpart = (double *)(ws + L.lpart);
-    d.sgpart = (double *)(ws + L.sgpart);
-    d.lgpart = (double *)(ws + L.lgpart);
-    d.scnt = (unsigned *)(ws + L.scnt);
-    d.lcnt = (unsigned *)(ws + L.lcnt);
-    d.stotal = (double *)(ws + L.stotal);
     d.ctl = (Ctl *)(ws + L.ctl);
     d.hist = (HistEntry *)(ws + L.hist);
     d.lo = p->lo;
@@ -271,9 +287,6 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     launch_transpose(row_ptr, col_idx, m, n, nnz, col_ptr, row_idx, (int *)(ws + L.a), s);
     launch_check_routes(col_ptr, n, p->hi, d.ctl, s);
     launch_init_state<T>(d, c_src, w_src, u_src, s);
-    launch_fill_int((int *)d.scnt, 0, (L.lcnt - L.scnt) / 4, s);
-    launch_fill_int((int *)d.lcnt, 0, (L.stotal - L.lcnt) / 4, s);
-    launch_fill_int((int *)d.stotal, 0, 2, s);
     HIP_TRY(hipGetLastError());
 
     // Workgroup tables from the two pointer arrays.
@@ -290,8 +303,75 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         return fail(PMP_ERR_SHAPE, "internal: block tables exceed their bound");
     HIP_TRY(hipMemcpyAsync((void *)d.sblk, sblk.data(), sblk.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((void *)d.lblk, lblk.data(), lblk.size() * 4, hipMemcpyHostToDevice, s));
+    d.binned = L.binned ? 1 : 0;
+    if (L.binned) {
+        // tile offsets and local indices of the binned message layout
+        d.P = L.bp.P;
+        d.Q = L.bp.Q;
+        d.LB = L.bp.LB;
+        d.SB = L.bp.SB;
+        d.mx = (T *)(ws + L.mx);
+        d.mv = (T *)(ws + L.mv);
+        d.lix = (const uint16_t *)(ws + L.lix);
+        d.six = (const uint16_t *)(ws + L.six);
+        d.ox = (const long long *)(ws + L.ox);
+        d.ov = (const long long *)(ws + L.ov);
+        const size_t tiles = (size_t)d.P * (size_t)d.Q + 1;
+        std::vector<int> hcolidx((size_t)nnz);
+        if (nnz) HIP_TRY(hipMemcpyAsync(hcolidx.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<long long> ox(tiles), ov(tiles);
+        std::vector<uint16_t> lix((size_t)nnz), six((size_t)nnz);
+        binned_build_host(hrow.data(), hcolidx.data(), m, n, L.bp, ox.data(), ov.data(), lix.data(),
+                          six.data());
+        HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 8, hipMemcpyHostToDevice, s));
+        if (nnz) {
+            HIP_TRY(hipMemcpyAsync((void *)d.lix, lix.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.six, six.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemsetAsync(d.mv, 0, (size_t)nnz * sizeof(T), s));   // v = 0 at the start
+        }
+        binned_configure();
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     return PMP_OK;
+}
+
+// One pass of either layout.
+template <typename T>
+void stream_pass(const Dev<T> &d, bool check, hipStream_t s)
+{
+    if (d.binned) launch_bin_stream<T>(d, check, s);
+    else launch_stream_pass<T>(d, check, s);
+}
+
+// The link pass; a check also reduces its residual partials and decides
+// (stop rule, rho balancing) right after it.
+template <typename T>
+void link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t s)
+{
+    if (d.binned) launch_bin_link<T>(d, mode, s);
+    else launch_link_pass<T>(d, mode, s);
+    if (mode == kCheck)
+        launch_check_finalize<T>(d, d.binned ? d.Q : d.nsb, d.binned ? d.P : d.nlb, delta, stop, s);
+}
+
+// After a check iteration: the u rescale of a balancing step (gather layout:
+// only needed at balancing iterations; binned layout: always, since the
+// check link pass leaves the link messages to this step).
+template <typename T>
+void after_check(const Dev<T> &d, bool adapt_iteration, hipStream_t s)
+{
+    if (d.binned) launch_bin_emit<T>(d, 1, s);
+    else if (adapt_iteration) launch_rescale<T>(d, s);
+}
+
+// Refresh the link messages from v after v changed outside an iteration.
+template <typename T>
+void refresh_messages(const Dev<T> &d, hipStream_t s)
+{
+    if (d.binned) launch_bin_emit<T>(d, 0, s);
 }
 
 // Queue iterations [h->iter_enq + 1, h->iter_enq + k] without a stop test;
@@ -305,12 +385,12 @@ void enqueue_iterations(pmp_handle *h, int k, hipStream_t s)
         const long long it = h->iter_enq + 1;
         const bool check = i == k || (adapt > 0 && it % adapt == 0);
         const bool next_check = i < k && (i + 1 == k || (adapt > 0 && (it + 1) % adapt == 0));
-        launch_stream_pass<T>(d, check, s);
+        stream_pass<T>(d, check, s);
         const int mode = check ? kCheck : (next_check ? kSave : kPlain);
-        launch_link_pass<T>(d, mode, it - h->iter_fin, 0, s);
+        link_pass<T>(d, mode, it - h->iter_fin, 0, s);
         if (check) {
             h->iter_fin = it;
-            if (adapt > 0 && it % adapt == 0) launch_rescale<T>(d, s);
+            after_check<T>(d, adapt > 0 && it % adapt == 0, s);
         }
         h->iter_enq = it;
     }
@@ -325,11 +405,12 @@ pmp_status build_graph(pmp_handle *h)
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 1; i <= ce; ++i) {
         const bool check = i == ce;
-        launch_stream_pass<T>(d, check, h->cap_stream);
+        stream_pass<T>(d, check, h->cap_stream);
         const int mode = check ? kCheck : (i == ce - 1 ? kSave : kPlain);
-        launch_link_pass<T>(d, mode, ce, 1, h->cap_stream);
+        link_pass<T>(d, mode, ce, 1, h->cap_stream);
     }
-    launch_rescale<T>(d, h->cap_stream);
+    if (d.binned) launch_bin_emit<T>(d, 1, h->cap_stream);
+    else launch_rescale<T>(d, h->cap_stream);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamEndCapture(h->cap_stream, &g));
     h->graph = g;
@@ -489,11 +570,12 @@ pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
             if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)((t - 1) / s) * L.state, true)) != PMP_OK)
                 return rc;
         launch_stream_pass<T>(d, false, st);
-        launch_link_pass<T>(d, kPlain, 0, 0, st);
+        launch_link_pass<T>(d, kPlain, st);
     }
     h->iter_enq += K;
     if ((rc = copy_state<T>(h, ws + L.final_state, true)) != PMP_OK) return rc;
     if (h->n) HIP_TRY(hipMemcpyAsync(ws + L.xK, d.x, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    refresh_messages<T>(d, st);
     launch_objective<T>(d, (double *)(ws + L.part), L.nobj, (double *)(ws + L.J), st);
     HIP_TRY(hipGetLastError());
     double jv = 0.0;
@@ -532,7 +614,7 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
                 HIP_TRY(hipMemcpyAsync(tape_x + (size_t)(t - t0 - 1) * h->n, d.x,
                                        (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
             launch_slack_mask<T>(d, tape_mu + (size_t)(t - t0 - 1) * h->m, st);
-            launch_link_pass<T>(d, kPlain, 0, 0, st);
+            launch_link_pass<T>(d, kPlain, st);
         }
         if (t1 < K)   // link step of iteration t1, deferred from the later segment
             launch_adj_link_only<T>(d, a, tape_mu + (size_t)(t1 - t0 - 1) * h->m, st);
@@ -545,6 +627,7 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
     launch_adj_out<T>(d, a, gc, gw, st);
     if ((rc = copy_state<T>(h, ws + L.final_state, false)) != PMP_OK) return rc;
     if (h->n) HIP_TRY(hipMemcpyAsync(d.x, ws + L.xK, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    refresh_messages<T>(d, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     return PMP_OK;
@@ -622,15 +705,14 @@ pmp_status time_kernels_impl(pmp_handle *h, int k, double *ms)
         const bool next_check = i < k && (i + 1 == k || (adapt > 0 && (it + 1) % adapt == 0));
         is_check[i - 1] = check;
         (void)hipEventRecord(ev[3 * (i - 1)], s);
-        launch_stream_pass<T>(d, check, s);
+        stream_pass<T>(d, check, s);
         (void)hipEventRecord(ev[3 * (i - 1) + 1], s);
-        launch_link_pass<T>(d, check ? kCheck : (next_check ? kSave : kPlain), it - h->iter_fin,
-                            0, s);
-        (void)hipEventRecord(ev[3 * (i - 1) + 2], s);
+        link_pass<T>(d, check ? kCheck : (next_check ? kSave : kPlain), it - h->iter_fin, 0, s);
         if (check) {
             h->iter_fin = it;
-            if (adapt > 0 && it % adapt == 0) launch_rescale<T>(d, s);
+            after_check<T>(d, adapt > 0 && it % adapt == 0, s);
         }
+        (void)hipEventRecord(ev[3 * (i - 1) + 2], s);
         h->iter_enq = it;
     }
     hipError_t e = hipStreamSynchronize(s);
@@ -667,18 +749,18 @@ pmp_status pmp_params_default(pmp_params *p)
     p->adapt_every = 50;
     p->check_every = 10;
     p->max_iter = 100000;
+    p->layout = PMP_LAYOUT_AUTO;
     return PMP_OK;
 }
 
 pmp_status pmp_workspace_size(const pmp_problem *problem, const pmp_params *params,
                               size_t *bytes)
 {
-    (void)params;
     if (!problem || !bytes) return fail(PMP_ERR_INVALID, "NULL argument");
     if (problem->m < 0 || problem->n < 0 || problem->nnz < 0 || problem->nnz >= (1LL << 31))
         return fail(PMP_ERR_SHAPE, "m, n >= 0 and 0 <= nnz < 2^31 required");
     const size_t sz = problem->dtype == PMP_F64 ? 8 : 4;
-    *bytes = plan(problem->m, problem->n, problem->nnz, sz).total;
+    *bytes = plan(problem->m, problem->n, problem->nnz, sz, params ? params->layout : 0).total;
     return PMP_OK;
 }
 
@@ -692,7 +774,7 @@ pmp_status pmp_setup(const pmp_problem *problem, const pmp_params *params, void 
     st = check_params(params);
     if (st != PMP_OK) return st;
     const size_t sz = problem->dtype == PMP_F64 ? 8 : 4;
-    const Layout L = plan(problem->m, problem->n, problem->nnz, sz);
+    const Layout L = plan(problem->m, problem->n, problem->nnz, sz, params->layout);
     if (!workspace || workspace_bytes < L.total)
         return fail(PMP_ERR_SHAPE, "workspace of %zu bytes needed, %zu given", L.total,
                     workspace_bytes);
@@ -828,8 +910,13 @@ pmp_status pmp_set_state(pmp_handle *h, const void *state)
     HIP_TRY(hipStreamSynchronize(s));
     launch_ctl_init(h->ctl, rho, c.eps_tol, c.mu, c.gamma, c.adapt_every, s);
     HIP_TRY(hipMemcpyAsync(&h->ctl->iter, &it, 8, hipMemcpyHostToDevice, s));
-    if (h->dtype == PMP_F32) launch_refresh_v<float>(h->df, s);
-    else launch_refresh_v<double>(h->dd, s);
+    if (h->dtype == PMP_F32) {
+        launch_refresh_v<float>(h->df, s);
+        refresh_messages<float>(h->df, s);
+    } else {
+        launch_refresh_v<double>(h->dd, s);
+        refresh_messages<double>(h->dd, s);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     h->iter_enq = h->iter_fin = it;
@@ -842,8 +929,8 @@ pmp_status pmp_update_params(pmp_handle *h, const pmp_params *params)
     pmp_status st = check_params(params);
     if (st != PMP_OK) return st;
     if (params->alpha != h->prm.alpha || params->check_every != h->prm.check_every ||
-        params->adapt_every != h->prm.adapt_every)
-        return fail(PMP_ERR_INVALID, "alpha, check_every and adapt_every are fixed at setup");
+        params->adapt_every != h->prm.adapt_every || params->layout != h->prm.layout)
+        return fail(PMP_ERR_INVALID, "alpha, check_every, adapt_every and layout are fixed at setup");
     h->prm.eps_abs = params->eps_abs;
     h->prm.mu = params->mu;
     h->prm.gamma = params->gamma;
@@ -918,6 +1005,14 @@ pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **
         if (zs) *zs = h->dd.zs;
         if (v) *v = h->dd.v;
     }
+    return PMP_OK;
+}
+
+pmp_status pmp_get_layout(pmp_handle *h, int32_t *layout)
+{
+    if (!h || !layout) return fail(PMP_ERR_INVALID, "NULL argument");
+    const int b = h->dtype == PMP_F32 ? h->df.binned : h->dd.binned;
+    *layout = b ? PMP_LAYOUT_BINNED : PMP_LAYOUT_GATHER;
     return PMP_OK;
 }
 

@@ -1,0 +1,173 @@
+// Device-side building blocks shared by the PMP kernels: reductions, the
+// proximal operators of Section III-E and the per-stream / per-link updates
+// of the compact over-relaxed iteration (Section III-D, III-G).
+#pragma once
+
+#include "pmp_internal.h"
+
+#include <cmath>
+
+namespace pmp {
+
+__device__ __forceinline__ int ld_stream(const int *p) { return __builtin_nontemporal_load(p); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over a workgroup of NT threads in a fixed order; the result is valid in
+// thread 0.  `sh` holds NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) r += sh[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) { return block_sum_n<kBlock>(v, sh); }
+
+// Stage tab[idx[i]] for i < cnt into LDS.  Every lane first loads its share of
+// the index stream, then issues all of its gathers, then writes LDS, so up to
+// kCap / kBlock gathers per lane are in flight together.
+template <typename T>
+__device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
+                                             const T *__restrict__ tab, T *sh, int cnt)
+{
+    constexpr int R = kCap / kBlock;
+    int id[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kBlock + threadIdx.x;
+        id[r] = i < cnt ? ld_stream(idx + i) : -1;
+    }
+    T val[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) val[r] = id[r] >= 0 ? tab[id[r]] : T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * kBlock + threadIdx.x;
+        if (i < cnt) sh[i] = val[r];
+    }
+}
+
+// Proximal operator of one traffic stream with L terminals and sum of
+// arguments S (Section III-E), clipped to the box.  wsig > 0: log utility
+// with weight wsig; wsig < 0: linear utility with weight -wsig.  For S < 0 the
+// log root uses the equal form 2w / (rho (sqrt(S^2 + 4wL/rho) - S)).
+__device__ __forceinline__ double prox_stream(double S, int L, double wsig, double rho,
+                                              double lo, double hi)
+{
+    if (L == 0) return hi;
+    double x;
+    const double dl = (double)L;
+    if (wsig > 0.0) {
+        const double disc = sqrt(S * S + 4.0 * wsig * dl / rho);
+        x = S >= 0.0 ? (S + disc) / (2.0 * dl) : 2.0 * wsig / (rho * (disc - S));
+    } else {
+        x = (S - wsig / rho) / dl;
+    }
+    return fmin(fmax(x, lo), hi);
+}
+
+template <typename T, bool CHECK>
+__device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, double vsum,
+                                                double rho)
+{
+    const double a = (double)d.a[j];
+    const double S = (double)L * a + vsum;
+    const T xt = (T)prox_stream(S, L, (double)d.wsig[j], rho, d.lo, d.hi);
+    const double xn = (double)xt;
+    double part = 0.0;
+    if (CHECK) {                       // dual residual: sum_j L_j (dx_j)^2
+        const double dx = xn - (double)d.x[j];
+        part = (double)L * dx * dx;
+    }
+    d.x[j] = xt;
+    d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
+    return part;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void link_update(const Dev<T> &d, int l, int deg, double y,
+                                            double &r2, double &s2)
+{
+    const double c = (double)d.c[l], u = (double)d.u[l];
+    const double b = (double)d.b[l], zs = (double)d.zs[l];
+    const double al = d.alpha;
+    const double ps = fmax(zs - u, -c);                 // slack prox
+    const double cnt = (double)deg + 1.0;               // |l| = d_l + 1
+    const double pbar = (y + ps) / cnt;                 // link average
+    const T bt = (T)(-al * pbar + (1.0 - al) * b);
+    const T ut = (T)(u + al * pbar);
+    d.b[l] = bt;
+    d.zs[l] = (T)(al * (ps - pbar) + (1.0 - al) * zs);
+    d.u[l] = ut;
+    d.v[l] = (T)((double)bt - (double)ut);
+    if (MODE == kCheck) {
+        // ||r||^2 = sum_l |l| pbar_l^2 and, with D the change since the
+        // previous iteration, the link part of ||s||^2 / rho^2:
+        // sum_{j on l} (Dx_j - Dpbar)^2 + (Dps - Dpbar)^2
+        //   = [sum_j Dx_j^2] + d Dpbar^2 - 2 Dpbar Dy + (Dps - Dpbar)^2,
+        // the bracket being added on the stream side.
+        const double yp = d.y_prev[l], pp = d.ps_prev[l];
+        const double dpb = pbar - (yp + pp) / cnt;
+        const double dy = y - yp, dps = ps - pp;
+        r2 += cnt * pbar * pbar;
+        s2 += (double)deg * dpb * dpb - 2.0 * dpb * dy + (dps - dpb) * (dps - dpb);
+    }
+    if (MODE != kPlain) {
+        d.y_prev[l] = y;
+        d.ps_prev[l] = ps;
+    }
+}
+
+// ---- residual reduction, stop rule and rho balancing ---------------------
+
+// Thread 0 of the check-finalize kernel: residual norms (Section III-F), the
+// stop rule, and residual balancing of rho (Section III-G).
+template <typename T>
+__device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, double ss)
+{
+    Ctl *c = d.ctl;
+    const double rho = c->rho;
+    const long long it = c->iter + delta;
+    const double r = sqrt(sr);
+    const double s = rho * sqrt(fmax(ss, 0.0));
+    c->iter = it;
+    c->r_norm = r;
+    c->s_norm = s;
+    c->ratio = 1.0;
+    HistEntry &h = d.hist[c->nhist % kHist];
+    h.iter = it;
+    h.r_norm = r;
+    h.s_norm = s;
+    h.rho = rho;
+    c->nhist += 1;
+    if (!isfinite(r) || !isfinite(s)) {
+        c->status = PMP_ERR_NUMERIC;
+        c->done = 1;
+    } else if (stop && r < c->eps_tol && s < c->eps_tol) {
+        c->status = PMP_OK;
+        c->done = 1;
+    } else if (c->adapt_every > 0 && it % c->adapt_every == 0) {
+        double rn = rho;
+        if (r > c->mu * s) rn = c->gamma * rho;
+        else if (s > c->mu * r) rn = rho / c->gamma;
+        c->ratio = rho / rn;
+        c->rho = rn;
+    }
+}
+
+}  // namespace pmp

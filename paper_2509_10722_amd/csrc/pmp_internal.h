@@ -18,9 +18,8 @@ constexpr int kBlock = 256;
 constexpr int kCap = 4096;
 // Device history ring of (iteration, ||r||, ||s||, rho), one entry per check.
 constexpr int kHist = 4096;
-// Residual partials are reduced in two levels: groups of kGroup workgroups,
-// then the group sums; the last arrival at each level does the adding.
-constexpr int kGroup = 256;
+// Threads of the kernel that reduces the residual partials of a check.
+constexpr int kFinThreads = 1024;
 
 // Device-resident control block.  Kernels read rho and the done flag from
 // here, so a captured graph stays valid while rho changes (Section III-G
@@ -59,9 +58,10 @@ enum : unsigned {
 };
 
 // Link-pass flavours: PLAIN does the PMP update only; SAVE also keeps y and
-// ps for the next iteration's residual; CHECK forms the residual partials
-// against the saved values, keeps the new ones, and the last workgroup to
-// finish reduces the partials and takes the stop / rho decisions.
+// ps for the next iteration's residual; CHECK forms per-workgroup residual
+// partials against the saved values and keeps the new ones.  The check's
+// finalize kernel then reduces the partials and takes the stop and rho
+// decisions.
 enum LinkMode : int { kPlain = 0, kSave = 1, kCheck = 2 };
 
 // Device pointers of one instance (all inside the caller's workspace).
@@ -81,14 +81,19 @@ struct Dev {
     int nsb, nlb;
     double *spart;                  // [nsb]   stream residual partials
     double *lpart;                  // [2 nlb] link residual partials
-    double *sgpart;                 // [ceil(nsb/256)]     group sums
-    double *lgpart;                 // [2 ceil(nlb/256)]   group sums
-    unsigned *scnt;                 // [ceil(nsb/256) + 1] arrival counters
-    unsigned *lcnt;                 // [ceil(nlb/256) + 1] arrival counters
-    double *stotal;                 // stream part of ||s||^2 / rho^2
     double lo, hi, alpha;
     Ctl *ctl;
     HistEntry *hist;
+    // Binned message layout (pmp_binned.hip); P link blocks of LB links and
+    // Q stream blocks of SB streams tile R into P x Q tiles.
+    int binned;                     // 1: iterations use the binned kernels
+    int P, Q, LB, SB;
+    T *mx;                          // [nnz] stream -> link messages, tiles p-major
+    T *mv;                          // [nnz] link -> stream messages, tiles q-major
+    const uint16_t *lix;            // [nnz] local link of each mx entry
+    const uint16_t *six;            // [nnz] local stream of each mv entry
+    const long long *ox;            // [P Q + 1] tile offsets in mx, p-major
+    const long long *ov;            // [Q P + 1] tile offsets in mv, q-major
 };
 
 // Adjoint (reverse-mode) vectors, all FP64, in the adjoint workspace.
@@ -106,7 +111,12 @@ struct AdjDev {
 template <typename T>
 void launch_stream_pass(const Dev<T> &d, bool check, hipStream_t s);
 template <typename T>
-void launch_link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t s);
+void launch_link_pass(const Dev<T> &d, int mode, hipStream_t s);
+// Reduce the partials of a check (nspart stream, nlpart link workgroups) and
+// take the stop / rho decisions.
+template <typename T>
+void launch_check_finalize(const Dev<T> &d, int nspart, int nlpart, long long delta, int stop,
+                           hipStream_t s);
 template <typename T>
 void launch_rescale(const Dev<T> &d, hipStream_t s);
 template <typename T>
@@ -121,6 +131,24 @@ template <typename T>
 void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s);
 template <typename T>
 void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s);
+
+// Binned layout (pmp_binned.hip).
+constexpr int kBinThreads = 1024;          // threads per binned workgroup
+constexpr int kBinMaxBlock = 10240;        // links / streams per binned workgroup
+struct BinnedPlan {
+    int P, Q, LB, SB;
+};
+BinnedPlan binned_plan(int m, int n);
+// Host construction of ox, ov, lix, six from the CSR pattern.
+void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
+                       long long *ox, long long *ov, uint16_t *lix, uint16_t *six);
+template <typename T>
+void launch_bin_stream(const Dev<T> &d, bool check, hipStream_t s);
+template <typename T>
+void launch_bin_link(const Dev<T> &d, int mode, hipStream_t s);
+template <typename T>
+void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s);
+void binned_configure();
 
 // Adjoint launchers (pmp_adjoint.hip).
 template <typename T>

@@ -12,180 +12,13 @@
 // staged in LDS, and then one lane per segment sums its run in FP64 in a
 // fixed order (no atomics; results are bitwise reproducible).  A segment
 // longer than kCap gets a workgroup of its own that strides over it.
-#include "pmp_internal.h"
+#include "pmp_device.h"
 
 #include <cmath>
 
 namespace pmp {
 
 namespace {
-
-__device__ __forceinline__ int ld_stream(const int *p) { return __builtin_nontemporal_load(p); }
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Sum over the workgroup in a fixed order; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double *sh)
-{
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) r += sh[i];
-    }
-    __syncthreads();
-    return r;
-}
-
-// Two-level arrival reduction of W doubles per workgroup.  Thread 0's v[] is
-// this workgroup's partial.  The last workgroup to arrive in a group of
-// kGroup adds the group's partials (in workgroup order), and the last group
-// to finish adds the group sums (in group order), so the total does not
-// depend on scheduling.  Returns true in that final workgroup, with the
-// totals in tot[] (thread 0).  Counters are left at zero.
-template <int W>
-__device__ bool reduce_arrive(const double (&v)[W], double *part, double *gpart, unsigned *cnt,
-                              int nblk, double *sred, double (&tot)[W])
-{
-    __shared__ int s_flag;
-    const int blk = blockIdx.x, g = blk / kGroup;
-    const int ng = (nblk + kGroup - 1) / kGroup;
-    const int gsize = min(kGroup, nblk - g * kGroup);
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < W; ++w) part[W * blk + w] = v[w];
-        __threadfence();
-        const unsigned prev = atomicAdd(&cnt[g], 1u);
-        s_flag = prev == (unsigned)gsize - 1u;
-    }
-    __syncthreads();
-    if (!s_flag) return false;
-    __threadfence();
-    double gs[W];
-    for (int w = 0; w < W; ++w) {
-        const double x = (int)threadIdx.x < gsize ? part[W * (g * kGroup + threadIdx.x) + w] : 0.0;
-        gs[w] = block_sum(x, sred);
-    }
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < W; ++w) gpart[W * g + w] = gs[w];
-        cnt[g] = 0u;
-        __threadfence();
-        const unsigned prev = atomicAdd(&cnt[ng], 1u);
-        s_flag = prev == (unsigned)ng - 1u;
-    }
-    __syncthreads();
-    if (!s_flag) return false;
-    __threadfence();
-    for (int w = 0; w < W; ++w) {
-        double x = 0.0;
-        for (int i = threadIdx.x; i < ng; i += kBlock) x += gpart[W * i + w];
-        tot[w] = block_sum(x, sred);
-    }
-    if (threadIdx.x == 0) cnt[ng] = 0u;
-    return true;
-}
-
-// Stage tab[idx[i]] for i < cnt into LDS.  Every lane first loads its share of
-// the index stream, then issues all of its gathers, then writes LDS, so up to
-// kCap / kBlock gathers per lane are in flight together.
-template <typename T>
-__device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
-                                             const T *__restrict__ tab, T *sh, int cnt)
-{
-    constexpr int R = kCap / kBlock;
-    int id[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = r * kBlock + threadIdx.x;
-        id[r] = i < cnt ? ld_stream(idx + i) : -1;
-    }
-    T val[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) val[r] = id[r] >= 0 ? tab[id[r]] : T(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = r * kBlock + threadIdx.x;
-        if (i < cnt) sh[i] = val[r];
-    }
-}
-
-// Proximal operator of one traffic stream with L terminals and sum of
-// arguments S (Section III-E), clipped to the box.  wsig > 0: log utility
-// with weight wsig; wsig < 0: linear utility with weight -wsig.  For S < 0 the
-// log root uses the equal form 2w / (rho (sqrt(S^2 + 4wL/rho) - S)).
-__device__ __forceinline__ double prox_stream(double S, int L, double wsig, double rho,
-                                              double lo, double hi)
-{
-    if (L == 0) return hi;
-    double x;
-    const double dl = (double)L;
-    if (wsig > 0.0) {
-        const double disc = sqrt(S * S + 4.0 * wsig * dl / rho);
-        x = S >= 0.0 ? (S + disc) / (2.0 * dl) : 2.0 * wsig / (rho * (disc - S));
-    } else {
-        x = (S - wsig / rho) / dl;
-    }
-    return fmin(fmax(x, lo), hi);
-}
-
-template <typename T, bool CHECK>
-__device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, double vsum,
-                                                double rho)
-{
-    const double a = (double)d.a[j];
-    const double S = (double)L * a + vsum;
-    const T xt = (T)prox_stream(S, L, (double)d.wsig[j], rho, d.lo, d.hi);
-    const double xn = (double)xt;
-    double part = 0.0;
-    if (CHECK) {                       // dual residual: sum_j L_j (dx_j)^2
-        const double dx = xn - (double)d.x[j];
-        part = (double)L * dx * dx;
-    }
-    d.x[j] = xt;
-    d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
-    return part;
-}
-
-template <typename T, int MODE>
-__device__ __forceinline__ void link_update(const Dev<T> &d, int l, int deg, double y,
-                                            double &r2, double &s2)
-{
-    const double c = (double)d.c[l], u = (double)d.u[l];
-    const double b = (double)d.b[l], zs = (double)d.zs[l];
-    const double al = d.alpha;
-    const double ps = fmax(zs - u, -c);                 // slack prox
-    const double cnt = (double)deg + 1.0;               // |l| = d_l + 1
-    const double pbar = (y + ps) / cnt;                 // link average
-    const T bt = (T)(-al * pbar + (1.0 - al) * b);
-    const T ut = (T)(u + al * pbar);
-    d.b[l] = bt;
-    d.zs[l] = (T)(al * (ps - pbar) + (1.0 - al) * zs);
-    d.u[l] = ut;
-    d.v[l] = (T)((double)bt - (double)ut);
-    if (MODE == kCheck) {
-        // ||r||^2 = sum_l |l| pbar_l^2 and, with D the change since the
-        // previous iteration, the link part of ||s||^2 / rho^2:
-        // sum_{j on l} (Dx_j - Dpbar)^2 + (Dps - Dpbar)^2
-        //   = [sum_j Dx_j^2] + d Dpbar^2 - 2 Dpbar Dy + (Dps - Dpbar)^2,
-        // the bracket being added on the stream side.
-        const double yp = d.y_prev[l], pp = d.ps_prev[l];
-        const double dpb = pbar - (yp + pp) / cnt;
-        const double dy = y - yp, dps = ps - pp;
-        r2 += cnt * pbar * pbar;
-        s2 += (double)deg * dpb * dpb - 2.0 * dpb * dy + (dps - dpb) * (dps - dpb);
-    }
-    if (MODE != kPlain) {
-        d.y_prev[l] = y;
-        d.ps_prev[l] = ps;
-    }
-}
 
 // ---- stream pass ---------------------------------------------------------
 
@@ -219,55 +52,15 @@ __global__ __launch_bounds__(kBlock) void k_stream_pass(Dev<T> d)
         if (threadIdx.x == 0) part = stream_update<T, CHECK>(d, s0, cnt, acc, rho);
     }
     if (CHECK) {
-        const double v[1] = {block_sum(part, sred)};
-        double tot[1];
-        if (reduce_arrive<1>(v, d.spart, d.sgpart, d.scnt, d.nsb, sred, tot) && threadIdx.x == 0)
-            *d.stotal = tot[0];
-    }
-}
-
-// ---- residual reduction, stop rule and rho balancing ---------------------
-
-// Thread 0 of the last link workgroup: residual norms (Section III-F), the
-// stop rule, and residual balancing of rho (Section III-G).
-template <typename T>
-__device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, double ss)
-{
-    ss += *d.stotal;
-    Ctl *c = d.ctl;
-    const double rho = c->rho;
-    const long long it = c->iter + delta;
-    const double r = sqrt(sr);
-    const double s = rho * sqrt(fmax(ss, 0.0));
-    c->iter = it;
-    c->r_norm = r;
-    c->s_norm = s;
-    c->ratio = 1.0;
-    HistEntry &h = d.hist[c->nhist % kHist];
-    h.iter = it;
-    h.r_norm = r;
-    h.s_norm = s;
-    h.rho = rho;
-    c->nhist += 1;
-    if (!isfinite(r) || !isfinite(s)) {
-        c->status = PMP_ERR_NUMERIC;
-        c->done = 1;
-    } else if (stop && r < c->eps_tol && s < c->eps_tol) {
-        c->status = PMP_OK;
-        c->done = 1;
-    } else if (c->adapt_every > 0 && it % c->adapt_every == 0) {
-        double rn = rho;
-        if (r > c->mu * s) rn = c->gamma * rho;
-        else if (s > c->mu * r) rn = rho / c->gamma;
-        c->ratio = rho / rn;
-        c->rho = rn;
+        part = block_sum(part, sred);
+        if (threadIdx.x == 0) d.spart[blk] = part;
     }
 }
 
 // ---- link pass -------------------------------------------------------------
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d, long long delta, int stop)
+__global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d)
 {
     if (d.ctl->done) return;
     __shared__ T sx[kCap];
@@ -295,11 +88,32 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d, long long delta,
         if (threadIdx.x == 0) link_update<T, MODE>(d, l0, cnt, acc, r2, s2);
     }
     if (MODE == kCheck) {
-        const double v[2] = {block_sum(r2, sred), block_sum(s2, sred)};
-        double tot[2];
-        if (reduce_arrive<2>(v, d.lpart, d.lgpart, d.lcnt, d.nlb, sred, tot) && threadIdx.x == 0)
-            finalize<T>(d, delta, stop, tot[0], tot[1]);
+        r2 = block_sum(r2, sred);
+        s2 = block_sum(s2, sred);
+        if (threadIdx.x == 0) {
+            d.lpart[2 * blk] = r2;
+            d.lpart[2 * blk + 1] = s2;
+        }
     }
+}
+
+// One workgroup: add the check's partials in a fixed order (each thread a
+// fixed stride, then a fixed tree), then the stop rule and rho balancing.
+template <typename T>
+__global__ __launch_bounds__(kFinThreads) void k_check_finalize(Dev<T> d, int nspart, int nlpart,
+                                                                long long delta, int stop)
+{
+    if (d.ctl->done) return;
+    __shared__ double sred[kFinThreads / 64];
+    double sr = 0.0, ss = 0.0;
+    for (int i = threadIdx.x; i < nlpart; i += kFinThreads) {
+        sr += d.lpart[2 * i];
+        ss += d.lpart[2 * i + 1];
+    }
+    for (int i = threadIdx.x; i < nspart; i += kFinThreads) ss += d.spart[i];
+    sr = block_sum_n<kFinThreads>(sr, sred);
+    ss = block_sum_n<kFinThreads>(ss, sred);
+    if (threadIdx.x == 0) finalize<T>(d, delta, stop, sr, ss);
 }
 
 // u <- (rho_old / rho_new) u after a balancing step (eq. (7)); v = b - u.
@@ -591,20 +405,28 @@ void launch_stream_pass(const Dev<T> &d, bool check, hipStream_t s)
 }
 
 template <typename T>
-void launch_link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t s)
+void launch_link_pass(const Dev<T> &d, int mode, hipStream_t s)
 {
     if (d.nlb == 0) return;
     switch (mode) {
     case kPlain:
-        hipLaunchKernelGGL((k_link_pass<T, kPlain>), dim3(d.nlb), dim3(kBlock), 0, s, d, delta, stop);
+        hipLaunchKernelGGL((k_link_pass<T, kPlain>), dim3(d.nlb), dim3(kBlock), 0, s, d);
         break;
     case kSave:
-        hipLaunchKernelGGL((k_link_pass<T, kSave>), dim3(d.nlb), dim3(kBlock), 0, s, d, delta, stop);
+        hipLaunchKernelGGL((k_link_pass<T, kSave>), dim3(d.nlb), dim3(kBlock), 0, s, d);
         break;
     default:
-        hipLaunchKernelGGL((k_link_pass<T, kCheck>), dim3(d.nlb), dim3(kBlock), 0, s, d, delta, stop);
+        hipLaunchKernelGGL((k_link_pass<T, kCheck>), dim3(d.nlb), dim3(kBlock), 0, s, d);
         break;
     }
+}
+
+template <typename T>
+void launch_check_finalize(const Dev<T> &d, int nspart, int nlpart, long long delta, int stop,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((k_check_finalize<T>), dim3(1), dim3(kFinThreads), 0, s, d, nspart, nlpart,
+                       delta, stop);
 }
 
 template <typename T>
@@ -721,7 +543,9 @@ void launch_fill_int(int *p, int value, size_t count, hipStream_t s)
 
 #define PMP_INSTANTIATE(T)                                                                  \
     template void launch_stream_pass<T>(const Dev<T> &, bool, hipStream_t);                \
-    template void launch_link_pass<T>(const Dev<T> &, int, long long, int, hipStream_t);   \
+    template void launch_link_pass<T>(const Dev<T> &, int, hipStream_t);                   \
+    template void launch_check_finalize<T>(const Dev<T> &, int, int, long long, int,       \
+                                           hipStream_t);                                    \
     template void launch_rescale<T>(const Dev<T> &, hipStream_t);                           \
     template void launch_refresh_v<T>(const Dev<T> &, hipStream_t);                         \
     template void launch_init_state<T>(const Dev<T> &, const T *, const T *,               \

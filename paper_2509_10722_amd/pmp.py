@@ -17,6 +17,7 @@ PMP_OK, PMP_ERR_INVALID, PMP_ERR_SHAPE, PMP_ERR_NOMEM, PMP_ERR_HIP, PMP_ERR_NUME
     PMP_NOT_CONVERGED, PMP_ERR_STATE = range(8)
 PMP_F32, PMP_F64 = 0, 1
 PMP_MEM_HOST, PMP_MEM_DEVICE = 0, 1
+PMP_LAYOUT_AUTO, PMP_LAYOUT_GATHER, PMP_LAYOUT_BINNED = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libpmp.so")
@@ -41,7 +42,8 @@ class pmp_params(ctypes.Structure):
     _fields_ = [("rho0", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("mu", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("eps_abs", ctypes.c_double), ("adapt_every", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class pmp_result(ctypes.Structure):
@@ -76,6 +78,7 @@ _SIGNATURES = {
     "pmp_forward_ckpt": [_P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t,
                          ctypes.POINTER(ctypes.c_double)],
     "pmp_backward": [_P, _P, _P],
+    "pmp_get_layout": [_P, ctypes.POINTER(ctypes.c_int32)],
     "pmp_destroy": [_P],
 }
 
@@ -270,6 +273,12 @@ class Solver:
         gw = self.torch.empty(max(self.n, 1), dtype=self.dtype, device=self.device)
         _check(self.lib.pmp_backward(self.handle, gc.data_ptr(), gw.data_ptr()), "pmp_backward")
         return gc, gw[: self.n]
+
+    def layout_in_use(self):
+        """'binned' or 'gather': the layout the library chose at setup."""
+        v = ctypes.c_int32()
+        _check(self.lib.pmp_get_layout(self.handle, ctypes.byref(v)), "pmp_get_layout")
+        return "binned" if v.value == PMP_LAYOUT_BINNED else "gather"
 
     def views(self):
         """Zero-copy tensors over the internal x, u, a, b, zs, v."""

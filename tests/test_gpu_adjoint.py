@@ -53,7 +53,9 @@ def _torch_unrolled(inst, c, w, K, alpha=1.6, rho=1.0):
         b = -alpha * pbar + (1 - alpha) * b
         zs = alpha * (ps - pbar) + (1 - alpha) * zs
         u = u + alpha * pbar
-    J = torch.sum(torch.where(log, w * torch.log(x), w * x))
+    # separate sums: a where() over both branches would send log(0) of clipped
+    # linear rates into the gradient as NaN
+    J = torch.sum(w[log] * torch.log(x[log])) + torch.sum(w[~log] * x[~log])
     return J, x
 
 

@@ -1,0 +1,99 @@
+"""The binned message layout (PMP_LAYOUT_BINNED) against the gather layout
+and the FP64 oracle.
+
+The binned kernels add FP32 messages into FP64 LDS sums; when each sum's
+addends span less than 2^24 in magnitude every partial sum is exact and the
+result equals the gather layout's sequential FP64 sum bit for bit, which is
+the case on these instances.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_10722_amd import instances as I
+from tests.gpu_util import host, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2509_10722_amd.pmp import (PMP_LAYOUT_BINNED, PMP_LAYOUT_GATHER,  # noqa: E402
+                                      Solver)
+
+
+def _run(inst, K, dtype, layout, **kw):
+    s = Solver(inst, dtype=dtype, layout=layout, **kw)
+    s.iterate(K)
+    r = s.residuals()
+    x, lam, slack = s.solution()
+    out = (host(x), host(lam), host(slack), r)
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("name,scale", [("medium", 0.2), ("large", 0.01), ("tiny", 1.0)])
+def test_binned_equals_gather_fp32(name, scale):
+    inst = I.make(name, scale=scale).rounded(np.float32)
+    K = 120
+    xb, lb, sb, rb = _run(inst, K, torch.float32, PMP_LAYOUT_BINNED)
+    xg, lg, sg, rg = _run(inst, K, torch.float32, PMP_LAYOUT_GATHER)
+    same = float(np.mean(xb == xg))
+    print(f"{name}: binned vs gather x {rel(xb, xg):.2e} lam {rel(lb, lg):.2e}, "
+          f"bitwise-equal x fraction {same:.6f}")
+    assert rel(xb, xg) <= 1e-6 and rel(lb, lg) <= 1e-6
+    assert abs(rb[0] - rg[0]) <= 1e-5 * rg[0] and abs(rb[1] - rg[1]) <= 1e-4 * rg[1]
+
+
+def test_binned_fp32_matches_oracle():
+    inst = I.medium(scale=0.2).rounded(np.float32)
+    K = 150
+    xb, lb, _, _ = _run(inst, K, torch.float32, PMP_LAYOUT_BINNED)
+    o = oracle.run(inst, K)
+    assert rel(xb, o["x"]) <= 1e-5 and rel(lb, o["lam"]) <= 1e-5
+
+
+def test_binned_fp64_matches_oracle():
+    inst = I.tiny()
+    K = 500
+    xb, lb, sb, _ = _run(inst, K, torch.float64, PMP_LAYOUT_BINNED)
+    o = oracle.run(inst, K)
+    assert rel(xb, o["x"]) <= 1e-10 and rel(lb, o["lam"]) <= 1e-10
+    assert rel(sb, o["slack"]) <= 1e-10
+
+
+def test_binned_solve_and_state():
+    inst = I.tiny()
+    s = Solver(inst, dtype=torch.float64, layout=PMP_LAYOUT_BINNED)
+    res = s.solve()
+    o = oracle.run(inst, 100000, stop=True)
+    assert res["converged"] and res["iterations"] == o["iterations"]
+    x, lam, _ = s.solution()
+    assert rel(host(x), o["x"]) <= 1e-10
+    st = s.get_state()
+    s.iterate(30)
+    x1, _, _ = s.solution()
+    s.set_state(st)
+    s.iterate(30)
+    x2, _, _ = s.solution()
+    assert torch.equal(x1, x2)
+    s.close()
+
+
+def test_binned_adjoint_matches_gather_adjoint():
+    inst = I.tiny(scale=0.5)
+    grads = []
+    for layout in (PMP_LAYOUT_BINNED, PMP_LAYOUT_GATHER):
+        s = Solver(inst, dtype=torch.float64, layout=layout, adapt_every=0)
+        s.iterate(17)                       # iterate, then differentiate from there
+        J = s.forward_ckpt(40, 9)
+        gc, gw = s.backward()
+        s.iterate(5)                        # the handle continues after backward
+        x, _, _ = s.solution()
+        grads.append((J, host(gc), host(gw), host(x)))
+        s.close()
+    (Jb, gcb, gwb, xb), (Jg, gcg, gwg, xg) = grads
+    assert abs(Jb - Jg) <= 1e-12 * abs(Jg)
+    assert rel(gcb, gcg) <= 1e-12 and rel(gwb, gwg) <= 1e-12
+    assert rel(xb, xg) <= 1e-12
