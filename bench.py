@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "PMP iters/sec + achieved HBM GB/s at n=2e7; time to 1e-4 rel. residual"
-KERNEL_SRC = os.path.join(ROOT, "paper_2509_10722_amd", "csrc", "pmp_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2509_10722_amd", "csrc")
 
 
 def bytes_model(n, m, nnz):
@@ -39,20 +39,24 @@ def bytes_model(n, m, nnz):
     return {"stream": stream, "link": link, "iteration": stream + link}
 
 
-def source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(files):
+    h = hashlib.sha256()
+    for fn in files:
+        with open(os.path.join(CSRC, fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
-    """Counter-measured HBM bytes per launch from profiles/, if taken on the
-    current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def load_traffic(kernel, layout, workload):
+    """Counter-measured HBM bytes per launch from profiles/ (FETCH_SIZE and
+    WRITE_SIZE, scaled by a calibration copy), if taken on the current source
+    of that kernel; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{layout}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_sha") != source_sha():
+    if t.get("source_sha") != source_sha(t.get("source_files", [])):
         return None
     return t.get("bytes_per_launch")
 
@@ -134,7 +138,7 @@ def main():
     dom = "link" if kt["link"] >= kt["stream"] else "stream"
     achieved = bm[dom] / (kt[dom] * 1e-3) / 1e9
     kname = {"link": "link_pass", "stream": "stream_pass"}[dom]
-    traffic = load_traffic(kname, args.config)
+    traffic = load_traffic(kname, used, args.config)
 
     out_tol = {}
     if not args.no_tol:

@@ -222,6 +222,46 @@ pmp_status pmp_forward_ckpt(pmp_handle *h, int32_t K, int32_t s, void *adj_works
  * NULL).  PMP_ERR_STATE without a preceding pmp_forward_ckpt. */
 pmp_status pmp_backward(pmp_handle *h, void *grad_c, void *grad_w);
 
+/* ---- batched solves of many uneven instances --------------------------
+ * The instances (host memory, one dtype, each with its own box) are
+ * concatenated block-diagonally and iterated together by one persistent,
+ * graph-captured kernel launch per pmp_batch_solve: every instance keeps its
+ * own rho, residuals, stop flag and iteration count (Section III-F/G applied
+ * per instance), and stopped instances drop out of the work.  Workgroup tiles
+ * never straddle instances; their nonzero limit (tile_cap, in [64, 4096]) is
+ * set per instance size class: m < class_m[0], m < class_m[1], larger. */
+typedef struct pmp_batch pmp_batch;
+typedef struct {
+    int32_t class_m[2];
+    int32_t tile_cap[3];
+} pmp_batch_options;
+
+/* Defaults: classes at m = 1e4 and 5e4, tile caps 1024 / 2048 / 4096. */
+pmp_status pmp_batch_options_default(pmp_batch_options *options);
+pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,
+                                    const pmp_params *params, const pmp_batch_options *options,
+                                    size_t *bytes);
+/* Validate (on the host) and lay out the instances in `workspace` (device
+ * memory, 256-byte aligned); state zero, rho = rho0 for every instance.
+ * Synchronises `stream`. */
+pmp_status pmp_batch_setup(int32_t count, const pmp_problem *problems, const pmp_params *params,
+                           const pmp_batch_options *options, void *workspace,
+                           size_t workspace_bytes, void *stream, pmp_batch **out);
+/* Run up to max_iter iterations of every instance that has not met the stop
+ * rule (checks every check_every iterations and at max_iter), continuing
+ * from the current state; results[count] (host) receive each instance's
+ * iterations in this call, residuals, rho and status.  Returns PMP_OK when
+ * every instance converged, PMP_NOT_CONVERGED otherwise, PMP_ERR_HIP if the
+ * kernel's bounded barrier wait expired. */
+pmp_status pmp_batch_solve(pmp_batch *b, int32_t max_iter, pmp_result *results);
+/* Solution of instance `index` into device buffers x[n_i], lambda[m_i],
+ * slack[m_i] (any may be NULL). */
+pmp_status pmp_batch_get_solution(pmp_batch *b, int32_t index, void *x, void *lambda,
+                                  void *slack);
+/* Back to the all-zero start, rho = rho0, for every instance. */
+pmp_status pmp_batch_reset(pmp_batch *b);
+pmp_status pmp_batch_destroy(pmp_batch *b);
+
 /* The layout chosen at setup (PMP_LAYOUT_GATHER or PMP_LAYOUT_BINNED). */
 pmp_status pmp_get_layout(pmp_handle *h, int32_t *layout);
 

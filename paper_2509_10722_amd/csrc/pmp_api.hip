@@ -151,6 +151,17 @@ std::string flag_text(unsigned f)
 
 }  // namespace
 
+pmp_status pmp::set_error(pmp_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
 struct pmp_handle {
     int m = 0, n = 0;
     long long nnz = 0;

@@ -1,0 +1,767 @@
+// Batched PMP: many uneven NUM instances in one persistent launch.
+//
+// The instances are concatenated block-diagonally (links and streams of each
+// instance kept together, indices global), so the stream and link passes of
+// all instances are the same segmented gather-sums as for one instance.  A
+// persistent kernel (grid sized to what the GPU holds at once) walks the
+// iterations: in each phase every workgroup takes every G-th tile of the
+// phase's tile list, skipping tiles of instances that have stopped, and a
+// grid barrier separates the phases.  Check iterations add a finalize phase
+// (workgroup i reduces instance i's tile partials in a fixed order and takes
+// its stop and rho decisions, Section III-F/G) and, at balancing iterations,
+// a rescale phase.  Tiles never straddle two instances; their size limit is
+// chosen per instance size class (see pmp_batch_options).
+//
+// Every barrier wait is bounded: a workgroup that waits too long sets an
+// abort flag and all workgroups leave the kernel, which then reports
+// PMP_ERR_HIP instead of hanging.
+#include "pmp_device.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace pmp {
+
+namespace {
+
+constexpr unsigned long long kSpinLimit = 1ull << 24;
+
+__device__ bool grid_sync(unsigned *bar, int *abort, unsigned nblocks)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = atomicAdd(&bar[0], 1u);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            atomicAdd(&bar[1], 1u);
+        } else {
+            unsigned long long spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit ||
+                    __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    atomicExch(abort, 1);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        s_ok = ok && !__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <typename T>
+__device__ __forceinline__ Dev<T> instance_view(const BDev<T> &d, int inst)
+{
+    Dev<T> di = d.g;
+    di.lo = d.lo[inst];
+    di.hi = d.hi[inst];
+    di.ctl = &d.ictl[inst];
+    di.hist = d.hist + (size_t)inst * kHist;
+    return di;
+}
+
+template <typename T, bool CHECK>
+__device__ void stream_tile(const BDev<T> &d, int tile, T *sv, double *sred)
+{
+    const int inst = d.st_inst[tile];
+    if (d.ictl[inst].done) return;
+    const Dev<T> di = instance_view(d, inst);
+    const int s0 = d.st_seg[tile], s1 = d.st_seg[tile + 1];
+    const int e0 = di.col_ptr[s0];
+    const int cnt = di.col_ptr[s1] - e0;
+    const double rho = d.ictl[inst].rho;
+    double part = 0.0;
+    if (cnt <= kCap) {
+        gather_stage<T>(di.row_idx + e0, di.v, sv, cnt);
+        __syncthreads();
+        const int j = s0 + (int)threadIdx.x;
+        if (j < s1) {
+            const int b = di.col_ptr[j] - e0, e = di.col_ptr[j + 1] - e0;
+            double acc = 0.0;
+            for (int k = b; k < e; ++k) acc += (double)sv[k];
+            part = stream_update<T, CHECK>(di, j, e - b, acc, rho);
+        }
+    } else {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kBlock)
+            acc += (double)di.v[ld_stream(di.row_idx + e0 + k)];
+        acc = block_sum(acc, sred);
+        if (threadIdx.x == 0) part = stream_update<T, CHECK>(di, s0, cnt, acc, rho);
+    }
+    if (CHECK) {
+        part = block_sum(part, sred);
+        if (threadIdx.x == 0) d.st_part[tile] = part;
+    }
+    __syncthreads();   // sv is reused by the next tile
+}
+
+template <typename T, int MODE>
+__device__ void link_tile(const BDev<T> &d, int tile, T *sx, double *sred)
+{
+    const int inst = d.lt_inst[tile];
+    if (d.ictl[inst].done) return;
+    const Dev<T> di = instance_view(d, inst);
+    const int l0 = d.lt_seg[tile], l1 = d.lt_seg[tile + 1];
+    const int e0 = di.row_ptr[l0];
+    const int cnt = di.row_ptr[l1] - e0;
+    double r2 = 0.0, s2 = 0.0;
+    if (cnt <= kCap) {
+        gather_stage<T>(di.col_idx + e0, di.x, sx, cnt);
+        __syncthreads();
+        const int l = l0 + (int)threadIdx.x;
+        if (l < l1) {
+            const int b = di.row_ptr[l] - e0, e = di.row_ptr[l + 1] - e0;
+            double acc = 0.0;
+            for (int k = b; k < e; ++k) acc += (double)sx[k];
+            link_update<T, MODE>(di, l, e - b, acc, r2, s2);
+        }
+    } else {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < cnt; k += kBlock)
+            acc += (double)di.x[ld_stream(di.col_idx + e0 + k)];
+        acc = block_sum(acc, sred);
+        if (threadIdx.x == 0) link_update<T, MODE>(di, l0, cnt, acc, r2, s2);
+    }
+    if (MODE == kCheck) {
+        r2 = block_sum(r2, sred);
+        s2 = block_sum(s2, sred);
+        if (threadIdx.x == 0) {
+            d.lt_part[2 * tile] = r2;
+            d.lt_part[2 * tile + 1] = s2;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int find_instance(const int *off, int B, int idx)
+{
+    int lo = 0, hi = B;   // off[lo] <= idx < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= idx) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int ce, int adapt)
+{
+    __shared__ T sv[kCap];
+    __shared__ double sred[kBlock / 64];
+    const unsigned G = gridDim.x;
+    // a solve call continues every instance from its current state
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.B; i += G * blockDim.x)
+        d.ictl[i].done = 0;
+    if (!grid_sync(d.bar, d.abort, G)) return;
+    long long last_check = 0;
+    for (int it = 1; it <= max_iter; ++it) {
+        const bool check = it % ce == 0 || it == max_iter;
+        const bool save = !check && ((it + 1) % ce == 0 || it + 1 == max_iter);
+        for (int t = blockIdx.x; t < d.nst; t += G) {
+            if (check) stream_tile<T, true>(d, t, sv, sred);
+            else stream_tile<T, false>(d, t, sv, sred);
+        }
+        if (!grid_sync(d.bar, d.abort, G)) return;
+        for (int t = blockIdx.x; t < d.nlt; t += G) {
+            if (check) link_tile<T, kCheck>(d, t, sv, sred);
+            else if (save) link_tile<T, kSave>(d, t, sv, sred);
+            else link_tile<T, kPlain>(d, t, sv, sred);
+        }
+        if (!grid_sync(d.bar, d.abort, G)) return;
+        if (!check) continue;
+        // finalize: one workgroup per instance, partials in tile order
+        const long long delta = it - last_check;
+        last_check = it;
+        for (int i = blockIdx.x; i < d.B; i += G) {
+            if (d.ictl[i].done) continue;
+            double ss = 0.0, sr = 0.0, sl = 0.0;
+            for (int t = d.inst_st[i] + threadIdx.x; t < d.inst_st[i + 1]; t += kBlock)
+                ss += d.st_part[t];
+            for (int t = d.inst_lt[i] + threadIdx.x; t < d.inst_lt[i + 1]; t += kBlock) {
+                sr += d.lt_part[2 * t];
+                sl += d.lt_part[2 * t + 1];
+            }
+            ss = block_sum(ss, sred);
+            sr = block_sum(sr, sred);
+            sl = block_sum(sl, sred);
+            if (threadIdx.x == 0) finalize<T>(instance_view(d, i), delta, 1, sr, ss + sl);
+            __syncthreads();
+        }
+        if (!grid_sync(d.bar, d.abort, G)) return;
+        int active = 0;
+        for (int i = 0; i < d.B; ++i) active += d.ictl[i].done ? 0 : 1;
+        if (active == 0) return;   // every workgroup sees the same flags
+        if (adapt > 0) {
+            // u <- (rho_old / rho_new) u where this check changed rho (eq. (7));
+            // finalize leaves ratio = 1 otherwise
+            for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.g.m; l += G * blockDim.x) {
+                const double r = d.ictl[find_instance(d.link_off, d.B, l)].ratio;
+                if (r != 1.0) {
+                    const T ut = (T)((double)d.g.u[l] * r);
+                    d.g.u[l] = ut;
+                    d.g.v[l] = (T)((double)d.g.b[l] - (double)ut);
+                }
+            }
+            if (!grid_sync(d.bar, d.abort, G)) return;
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int adapt_every,
+                  hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch<T>), dim3(grid), dim3(kBlock), 0, s, d, max_iter, check_every,
+                       adapt_every);
+}
+
+template <typename T>
+int batch_grid_size(int device)
+{
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch<T>, kBlock, 0) !=
+        hipSuccess)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    // at most 4 resident workgroups per CU take part: enough to cover latency,
+    // few enough to keep the barriers short
+    return std::min(per_cu, 4) * cus;
+}
+
+template void launch_batch<float>(const BDev<float> &, int, int, int, int, hipStream_t);
+template void launch_batch<double>(const BDev<double> &, int, int, int, int, hipStream_t);
+template int batch_grid_size<float>(int);
+template int batch_grid_size<double>(int);
+
+
+// ---- host side ----------------------------------------------------------------
+
+namespace {
+
+#define BATCH_TRY(expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return set_error(PMP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlignB = 256;
+size_t align_b(size_t v) { return (v + kAlignB - 1) / kAlignB * kAlignB; }
+
+struct BatchSizes {
+    long long M = 0, N = 0, NNZ = 0;
+    int B = 0;
+};
+
+struct BatchLayout {
+    size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
+    size_t link_off, stream_off, lo, hi, ictl, hist, st_seg, st_inst, lt_seg, lt_inst;
+    size_t inst_st, inst_lt, st_part, lt_part, bar, util, total;
+    long long nst_max, nlt_max;
+};
+
+BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap)
+{
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_b(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    L.nst_max = z.N / kBlock + 2 * z.NNZ / min_cap + 2LL * z.B + 2;
+    L.nlt_max = z.M / kBlock + 2 * z.NNZ / min_cap + 2LL * z.B + 2;
+    const size_t M = (size_t)z.M, N = (size_t)z.N, E = (size_t)z.NNZ, B = (size_t)z.B;
+    L.row_ptr = take((M + 1) * 4);
+    L.col_idx = take(E * 4);
+    L.col_ptr = take((N + 1) * 4);
+    L.row_idx = take(E * 4);
+    L.c = take(M * sz);
+    L.wsig = take(N * sz);
+    L.a = take(std::max(N * sz, transpose_scratch_ints((int)N) * 4));
+    L.x = take(N * sz);
+    L.b = take(M * sz);
+    L.zs = take(M * sz);
+    L.u = take(M * sz);
+    L.v = take(M * sz);
+    L.y_prev = take(M * 8);
+    L.ps_prev = take(M * 8);
+    L.link_off = take((B + 1) * 4);
+    L.stream_off = take((B + 1) * 4);
+    L.lo = take(B * 8);
+    L.hi = take(B * 8);
+    L.ictl = take(B * sizeof(Ctl));
+    L.hist = take(B * kHist * sizeof(HistEntry));
+    L.st_seg = take(((size_t)L.nst_max + 1) * 4);
+    L.st_inst = take((size_t)L.nst_max * 4);
+    L.lt_seg = take(((size_t)L.nlt_max + 1) * 4);
+    L.lt_inst = take((size_t)L.nlt_max * 4);
+    L.inst_st = take((B + 1) * 4);
+    L.inst_lt = take((B + 1) * 4);
+    L.st_part = take((size_t)L.nst_max * 8);
+    L.lt_part = take((size_t)L.nlt_max * 16);
+    L.bar = take(16);
+    L.util = take(N);
+    L.total = off;
+    return L;
+}
+
+bool sizes_of(int count, const pmp_problem *pr, BatchSizes &z)
+{
+    z = BatchSizes{};
+    z.B = count;
+    for (int i = 0; i < count; ++i) {
+        if (pr[i].m < 1 || pr[i].n < 0 || pr[i].nnz < 0) return false;
+        z.M += pr[i].m;
+        z.N += pr[i].n;
+        z.NNZ += pr[i].nnz;
+    }
+    return z.M < (1LL << 31) && z.N < (1LL << 31) && z.NNZ < (1LL << 31);
+}
+
+int class_cap(const pmp_batch_options *o, int m)
+{
+    const int c = m < o->class_m[0] ? 0 : (m < o->class_m[1] ? 1 : 2);
+    return o->tile_cap[c];
+}
+
+// Greedy tiles over segments [first, last) of one instance: at most kBlock
+// segments and `cap` nonzeros each (a longer segment alone).
+void tiles_for(const std::vector<int> &ptr, int first, int last, int cap, int inst,
+               std::vector<int> &seg, std::vector<int> &owner)
+{
+    int s = first;
+    while (s < last) {
+        int e = s;
+        long long cnt = 0;
+        while (e < last && e - s < kBlock && cnt + (ptr[e + 1] - ptr[e]) <= cap) {
+            cnt += ptr[e + 1] - ptr[e];
+            ++e;
+        }
+        if (e == s) e = s + 1;
+        seg.push_back(e);
+        owner.push_back(inst);
+        s = e;
+    }
+}
+
+pmp_status validate_host(const pmp_problem &p, int i)
+{
+    if (p.memory != PMP_MEM_HOST) return set_error(PMP_ERR_INVALID, "batch instance %d: host memory required", i);
+    if (!(p.lo >= 0.0) || !std::isfinite(p.lo) || !(p.hi > p.lo))
+        return set_error(PMP_ERR_INVALID, "batch instance %d: box must satisfy 0 <= lo < hi", i);
+    if (p.row_ptr[0] != 0 || p.row_ptr[p.m] != p.nnz)
+        return set_error(PMP_ERR_INVALID, "batch instance %d: row_ptr must run from 0 to nnz", i);
+    std::vector<int> deg((size_t)p.n, 0);
+    for (int l = 0; l < p.m; ++l) {
+        if (p.row_ptr[l + 1] < p.row_ptr[l]) return set_error(PMP_ERR_INVALID, "batch instance %d: row_ptr decreases", i);
+        int prev = -1;
+        for (int k = p.row_ptr[l]; k < p.row_ptr[l + 1]; ++k) {
+            const int j = p.col_idx[k];
+            if (j < 0 || j >= p.n) return set_error(PMP_ERR_INVALID, "batch instance %d: col_idx out of range", i);
+            if (j <= prev) return set_error(PMP_ERR_INVALID, "batch instance %d: col_idx not strictly increasing in a row", i);
+            prev = j;
+            deg[(size_t)j]++;
+        }
+    }
+    const size_t sz = p.dtype == PMP_F64 ? 8 : 4;
+    for (int l = 0; l < p.m; ++l) {
+        const double c = sz == 8 ? ((const double *)p.c)[l] : ((const float *)p.c)[l];
+        if (!(c > 0.0) || !std::isfinite(c)) return set_error(PMP_ERR_INVALID, "batch instance %d: capacities must be finite and > 0", i);
+    }
+    for (int j = 0; j < p.n; ++j) {
+        const double w = sz == 8 ? ((const double *)p.w)[j] : ((const float *)p.w)[j];
+        if (!(w > 0.0) || !std::isfinite(w)) return set_error(PMP_ERR_INVALID, "batch instance %d: weights must be finite and > 0", i);
+        if (p.utility[j] > 1) return set_error(PMP_ERR_INVALID, "batch instance %d: utility must be 0 or 1", i);
+        if (deg[(size_t)j] == 0 && std::isinf(p.hi))
+            return set_error(PMP_ERR_INVALID, "batch instance %d: a stream with an empty route needs a finite hi", i);
+    }
+    return PMP_OK;
+}
+
+}  // namespace
+
+}  // namespace pmp
+
+using namespace pmp;
+
+struct pmp_batch {
+    int B = 0;
+    pmp_dtype dtype = PMP_F32;
+    pmp_params prm{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    BDev<float> bf{};
+    BDev<double> bd{};
+    std::vector<int> m, n, link_off, stream_off;
+    std::vector<long long> nnz, iter_base;
+    std::vector<double> eps_tol;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_iters = -1;
+};
+
+namespace {
+
+template <typename T>
+BDev<T> &bdev_of(pmp_batch *b);
+template <>
+BDev<float> &bdev_of<float>(pmp_batch *b) { return b->bf; }
+template <>
+BDev<double> &bdev_of<double>(pmp_batch *b) { return b->bd; }
+
+template <typename T>
+pmp_status batch_init_ctl(pmp_batch *b)
+{
+    BDev<T> &d = bdev_of<T>(b);
+    std::vector<Ctl> h((size_t)b->B);
+    for (int i = 0; i < b->B; ++i) {
+        Ctl &c = h[(size_t)i];
+        std::memset(&c, 0, sizeof c);
+        c.rho = b->prm.rho0;
+        c.ratio = 1.0;
+        c.eps_tol = b->eps_tol[(size_t)i];
+        c.mu = b->prm.mu;
+        c.gamma = b->prm.gamma;
+        c.adapt_every = b->prm.adapt_every;
+        c.status = PMP_OK;
+    }
+    BATCH_TRY(hipMemcpyAsync(d.ictl, h.data(), sizeof(Ctl) * h.size(), hipMemcpyHostToDevice, b->stream));
+    std::fill(b->iter_base.begin(), b->iter_base.end(), 0);
+    return PMP_OK;
+}
+
+template <typename T>
+pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch_options *opt,
+                            char *ws, const BatchSizes &z)
+{
+    const int min_cap = std::min(opt->tile_cap[0], std::min(opt->tile_cap[1], opt->tile_cap[2]));
+    const BatchLayout L = batch_plan(z, sizeof(T), min_cap);
+    hipStream_t s = b->stream;
+    BDev<T> &d = bdev_of<T>(b);
+    Dev<T> &g = d.g;
+    const int M = (int)z.M, N = (int)z.N, B = z.B;
+    const long long E = z.NNZ;
+    // concatenated host arrays (global indices)
+    std::vector<int> row_ptr((size_t)M + 1), col_idx((size_t)E);
+    std::vector<T> c((size_t)M), w((size_t)N);
+    std::vector<uint8_t> util((size_t)N);
+    std::vector<double> lo((size_t)B), hi((size_t)B);
+    b->link_off.assign((size_t)B + 1, 0);
+    b->stream_off.assign((size_t)B + 1, 0);
+    long long eo = 0;
+    for (int i = 0; i < B; ++i) {
+        const pmp_problem &p = pr[i];
+        const int lo_l = b->link_off[(size_t)i], lo_s = b->stream_off[(size_t)i];
+        for (int l = 0; l < p.m; ++l) {
+            row_ptr[(size_t)lo_l + l] = (int)(eo + p.row_ptr[l]);
+            c[(size_t)lo_l + l] = ((const T *)p.c)[l];
+        }
+        for (long long k = 0; k < p.nnz; ++k) col_idx[(size_t)(eo + k)] = p.col_idx[k] + lo_s;
+        for (int j = 0; j < p.n; ++j) {
+            w[(size_t)lo_s + j] = ((const T *)p.w)[j];
+            util[(size_t)lo_s + j] = p.utility[j];
+        }
+        lo[(size_t)i] = p.lo;
+        hi[(size_t)i] = p.hi;
+        eo += p.nnz;
+        b->link_off[(size_t)i + 1] = lo_l + p.m;
+        b->stream_off[(size_t)i + 1] = lo_s + p.n;
+    }
+    row_ptr[(size_t)M] = (int)E;
+    // device views
+    g = Dev<T>{};
+    g.m = M;
+    g.n = N;
+    g.nnz = E;
+    g.row_ptr = (int *)(ws + L.row_ptr);
+    g.col_idx = (int *)(ws + L.col_idx);
+    g.col_ptr = (int *)(ws + L.col_ptr);
+    g.row_idx = (int *)(ws + L.row_idx);
+    g.c = (T *)(ws + L.c);
+    g.wsig = (T *)(ws + L.wsig);
+    g.a = (T *)(ws + L.a);
+    g.x = (T *)(ws + L.x);
+    g.b = (T *)(ws + L.b);
+    g.zs = (T *)(ws + L.zs);
+    g.u = (T *)(ws + L.u);
+    g.v = (T *)(ws + L.v);
+    g.y_prev = (double *)(ws + L.y_prev);
+    g.ps_prev = (double *)(ws + L.ps_prev);
+    g.alpha = b->prm.alpha;
+    d.B = B;
+    d.link_off = (int *)(ws + L.link_off);
+    d.stream_off = (int *)(ws + L.stream_off);
+    d.lo = (double *)(ws + L.lo);
+    d.hi = (double *)(ws + L.hi);
+    d.ictl = (Ctl *)(ws + L.ictl);
+    d.hist = (HistEntry *)(ws + L.hist);
+    d.st_seg = (int *)(ws + L.st_seg);
+    d.st_inst = (int *)(ws + L.st_inst);
+    d.lt_seg = (int *)(ws + L.lt_seg);
+    d.lt_inst = (int *)(ws + L.lt_inst);
+    d.inst_st = (int *)(ws + L.inst_st);
+    d.inst_lt = (int *)(ws + L.inst_lt);
+    d.st_part = (double *)(ws + L.st_part);
+    d.lt_part = (double *)(ws + L.lt_part);
+    d.bar = (unsigned *)(ws + L.bar);
+    d.abort = (int *)(ws + L.bar + 8);
+    BATCH_TRY(hipMemcpyAsync((void *)g.row_ptr, row_ptr.data(), row_ptr.size() * 4, hipMemcpyHostToDevice, s));
+    if (E) BATCH_TRY(hipMemcpyAsync((void *)g.col_idx, col_idx.data(), (size_t)E * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)g.c, c.data(), c.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (N) BATCH_TRY(hipMemcpyAsync((void *)g.wsig, w.data(), w.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (N) BATCH_TRY(hipMemcpyAsync(ws + L.util, util.data(), util.size(), hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.link_off, b->link_off.data(), ((size_t)B + 1) * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.stream_off, b->stream_off.data(), ((size_t)B + 1) * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.lo, lo.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.hi, hi.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
+    launch_transpose(g.row_ptr, g.col_idx, M, N, E, (int *)g.col_ptr, (int *)g.row_idx, (int *)(ws + L.a), s);
+    launch_init_state<T>(g, g.c, g.wsig, (const uint8_t *)(ws + L.util), s);
+    launch_fill_int((int *)d.bar, 0, 4, s);
+    BATCH_TRY(hipGetLastError());
+    std::vector<int> col_ptr((size_t)N + 1);
+    BATCH_TRY(hipMemcpyAsync(col_ptr.data(), g.col_ptr, col_ptr.size() * 4, hipMemcpyDeviceToHost, s));
+    BATCH_TRY(hipStreamSynchronize(s));
+    // tiles per instance, sized by the instance's class
+    std::vector<int> st_seg{0}, st_inst, lt_seg{0}, lt_inst, inst_st{0}, inst_lt{0};
+    for (int i = 0; i < B; ++i) {
+        const int cap = class_cap(opt, b->m[(size_t)i]);
+        tiles_for(col_ptr, b->stream_off[(size_t)i], b->stream_off[(size_t)i + 1], cap, i, st_seg, st_inst);
+        tiles_for(row_ptr, b->link_off[(size_t)i], b->link_off[(size_t)i + 1], cap, i, lt_seg, lt_inst);
+        inst_st.push_back((int)st_inst.size());
+        inst_lt.push_back((int)lt_inst.size());
+    }
+    d.nst = (int)st_inst.size();
+    d.nlt = (int)lt_inst.size();
+    if (d.nst > L.nst_max || d.nlt > L.nlt_max)
+        return set_error(PMP_ERR_SHAPE, "internal: batch tile tables exceed their bound");
+    BATCH_TRY(hipMemcpyAsync((void *)d.st_seg, st_seg.data(), st_seg.size() * 4, hipMemcpyHostToDevice, s));
+    if (d.nst) BATCH_TRY(hipMemcpyAsync((void *)d.st_inst, st_inst.data(), st_inst.size() * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.lt_seg, lt_seg.data(), lt_seg.size() * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.lt_inst, lt_inst.data(), lt_inst.size() * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.inst_st, inst_st.data(), inst_st.size() * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.inst_lt, inst_lt.data(), inst_lt.size() * 4, hipMemcpyHostToDevice, s));
+    pmp_status st = batch_init_ctl<T>(b);
+    if (st != PMP_OK) return st;
+    int dev = 0;
+    BATCH_TRY(hipGetDevice(&dev));
+    b->grid = batch_grid_size<T>(dev);
+    if (b->grid < 1) return set_error(PMP_ERR_HIP, "occupancy query for the batch kernel failed");
+    BATCH_TRY(hipStreamSynchronize(s));
+    return PMP_OK;
+}
+
+template <typename T>
+pmp_status batch_solve_impl(pmp_batch *b, int max_iter, pmp_result *res)
+{
+    BDev<T> &d = bdev_of<T>(b);
+    if (max_iter > 0) {
+        if (b->graph_iters != max_iter) {
+            if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->graph_exec = nullptr;
+            b->graph = nullptr;
+            BATCH_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            // barrier counters and abort flag start at zero in every launch
+            launch_fill_int((int *)d.bar, 0, 4, b->cap_stream);
+            launch_batch<T>(d, b->grid, max_iter, b->prm.check_every, b->prm.adapt_every, b->cap_stream);
+            BATCH_TRY(hipStreamEndCapture(b->cap_stream, &b->graph));
+            BATCH_TRY(hipGraphInstantiateWithFlags(&b->graph_exec, b->graph, 0));
+            b->graph_iters = max_iter;
+        }
+        BATCH_TRY(hipGraphLaunch(b->graph_exec, b->stream));
+    }
+    std::vector<Ctl> h((size_t)b->B);
+    int abort_flag = 0;
+    BATCH_TRY(hipMemcpyAsync(h.data(), d.ictl, sizeof(Ctl) * h.size(), hipMemcpyDeviceToHost, b->stream));
+    BATCH_TRY(hipMemcpyAsync(&abort_flag, d.abort, 4, hipMemcpyDeviceToHost, b->stream));
+    BATCH_TRY(hipStreamSynchronize(b->stream));
+    if (abort_flag) return set_error(PMP_ERR_HIP, "batch kernel: a grid barrier wait exceeded its bound");
+    bool all = true;
+    for (int i = 0; i < b->B; ++i) {
+        const Ctl &c = h[(size_t)i];
+        const pmp_status st = c.done ? (pmp_status)c.status : PMP_NOT_CONVERGED;
+        if (res) {
+            res[i].iterations = c.iter - b->iter_base[(size_t)i];
+            res[i].r_norm = c.r_norm;
+            res[i].s_norm = c.s_norm;
+            res[i].eps_tol = c.eps_tol;
+            res[i].rho = c.rho;
+            res[i].status = st;
+        }
+        b->iter_base[(size_t)i] = c.iter;
+        if (st != PMP_OK) all = false;
+    }
+    return all ? PMP_OK : PMP_NOT_CONVERGED;
+}
+
+template <typename T>
+pmp_status batch_solution_impl(pmp_batch *b, int i, T *x, T *lambda, T *slack)
+{
+    BDev<T> &d = bdev_of<T>(b);
+    Dev<T> di = d.g;
+    const int l0 = b->link_off[(size_t)i], s0 = b->stream_off[(size_t)i];
+    di.m = b->m[(size_t)i];
+    di.n = b->n[(size_t)i];
+    di.x += s0;
+    di.u += l0;
+    di.c += l0;
+    di.ps_prev += l0;
+    di.ctl = d.ictl + i;
+    launch_solution<T>(di, x, lambda, slack, b->stream);
+    BATCH_TRY(hipGetLastError());
+    BATCH_TRY(hipStreamSynchronize(b->stream));
+    return PMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pmp_status pmp_batch_options_default(pmp_batch_options *o)
+{
+    if (!o) return set_error(PMP_ERR_INVALID, "options is NULL");
+    o->class_m[0] = 10000;
+    o->class_m[1] = 50000;
+    o->tile_cap[0] = 1024;
+    o->tile_cap[1] = 2048;
+    o->tile_cap[2] = 4096;
+    return PMP_OK;
+}
+
+static pmp_status check_batch_args(int32_t count, const pmp_problem *pr, const pmp_params *prm,
+                                   const pmp_batch_options *opt, BatchSizes &z)
+{
+    if (count < 1 || !pr || !prm || !opt) return set_error(PMP_ERR_INVALID, "bad batch arguments");
+    for (int c = 0; c < 3; ++c)
+        if (opt->tile_cap[c] < 64 || opt->tile_cap[c] > kCap)
+            return set_error(PMP_ERR_INVALID, "tile_cap must be in [64, %d]", kCap);
+    for (int i = 1; i < count; ++i)
+        if (pr[i].dtype != pr[0].dtype) return set_error(PMP_ERR_INVALID, "batch instances must share the dtype");
+    if (!sizes_of(count, pr, z)) return set_error(PMP_ERR_SHAPE, "batch sizes out of range (m >= 1; totals < 2^31)");
+    if (prm->check_every < 1 || prm->adapt_every < 0 ||
+        (prm->adapt_every > 0 && prm->adapt_every % prm->check_every))
+        return set_error(PMP_ERR_INVALID, "adapt_every must be 0 or a multiple of check_every");
+    if (!(prm->rho0 > 0.0) || !(prm->alpha > 0.0 && prm->alpha < 2.0) || !(prm->mu > 1.0) || !(prm->gamma > 1.0))
+        return set_error(PMP_ERR_INVALID, "rho0 > 0, alpha in (0, 2), mu > 1 and gamma > 1 required");
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,
+                                    const pmp_params *params, const pmp_batch_options *options,
+                                    size_t *bytes)
+{
+    BatchSizes z;
+    pmp_status st = check_batch_args(count, problems, params, options, z);
+    if (st != PMP_OK) return st;
+    if (!bytes) return set_error(PMP_ERR_INVALID, "bytes is NULL");
+    const int min_cap = std::min(options->tile_cap[0], std::min(options->tile_cap[1], options->tile_cap[2]));
+    *bytes = batch_plan(z, problems[0].dtype == PMP_F64 ? 8 : 4, min_cap).total;
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_setup(int32_t count, const pmp_problem *problems, const pmp_params *params,
+                           const pmp_batch_options *options, void *workspace,
+                           size_t workspace_bytes, void *stream, pmp_batch **out)
+{
+    if (!out) return set_error(PMP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    BatchSizes z;
+    pmp_status st = check_batch_args(count, problems, params, options, z);
+    if (st != PMP_OK) return st;
+    for (int i = 0; i < count; ++i)
+        if ((st = validate_host(problems[i], i)) != PMP_OK) return st;
+    const size_t sz = problems[0].dtype == PMP_F64 ? 8 : 4;
+    const int min_cap = std::min(options->tile_cap[0], std::min(options->tile_cap[1], options->tile_cap[2]));
+    const size_t need = batch_plan(z, sz, min_cap).total;
+    if (!workspace || workspace_bytes < need)
+        return set_error(PMP_ERR_SHAPE, "batch workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    if ((uintptr_t)workspace % kAlignB) return set_error(PMP_ERR_INVALID, "workspace must be 256-byte aligned");
+    pmp_batch *b = new (std::nothrow) pmp_batch();
+    if (!b) return set_error(PMP_ERR_NOMEM, "batch handle allocation failed");
+    b->B = count;
+    b->dtype = problems[0].dtype;
+    b->prm = *params;
+    b->stream = (hipStream_t)stream;
+    b->iter_base.assign((size_t)count, 0);
+    for (int i = 0; i < count; ++i) {
+        b->m.push_back(problems[i].m);
+        b->n.push_back(problems[i].n);
+        b->nnz.push_back(problems[i].nnz);
+        b->eps_tol.push_back(params->eps_abs * std::sqrt((double)problems[i].nnz + problems[i].m));
+    }
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return set_error(PMP_ERR_HIP, "hipStreamCreateWithFlags failed");
+    }
+    st = b->dtype == PMP_F32 ? batch_setup_impl<float>(b, problems, options, (char *)workspace, z)
+                             : batch_setup_impl<double>(b, problems, options, (char *)workspace, z);
+    if (st != PMP_OK) {
+        pmp_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_solve(pmp_batch *b, int32_t max_iter, pmp_result *results)
+{
+    if (!b || max_iter < 0) return set_error(PMP_ERR_INVALID, "bad argument");
+    return b->dtype == PMP_F32 ? batch_solve_impl<float>(b, max_iter, results)
+                               : batch_solve_impl<double>(b, max_iter, results);
+}
+
+pmp_status pmp_batch_get_solution(pmp_batch *b, int32_t index, void *x, void *lambda, void *slack)
+{
+    if (!b || index < 0 || index >= b->B) return set_error(PMP_ERR_INVALID, "bad argument");
+    return b->dtype == PMP_F32
+               ? batch_solution_impl<float>(b, index, (float *)x, (float *)lambda, (float *)slack)
+               : batch_solution_impl<double>(b, index, (double *)x, (double *)lambda, (double *)slack);
+}
+
+pmp_status pmp_batch_reset(pmp_batch *b)
+{
+    if (!b) return set_error(PMP_ERR_INVALID, "batch is NULL");
+    pmp_status st;
+    if (b->dtype == PMP_F32) {
+        launch_zero_state<float>(b->bf.g, b->stream);
+        st = batch_init_ctl<float>(b);
+    } else {
+        launch_zero_state<double>(b->bd.g, b->stream);
+        st = batch_init_ctl<double>(b);
+    }
+    if (st != PMP_OK) return st;
+    BATCH_TRY(hipGetLastError());
+    BATCH_TRY(hipStreamSynchronize(b->stream));
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_destroy(pmp_batch *b)
+{
+    if (!b) return PMP_OK;
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return PMP_OK;
+}
+
+}  // extern "C"

@@ -122,6 +122,8 @@ void launch_rescale(const Dev<T> &d, hipStream_t s);
 template <typename T>
 void launch_refresh_v(const Dev<T> &d, hipStream_t s);
 template <typename T>
+void launch_zero_state(const Dev<T> &d, hipStream_t s);
+template <typename T>
 void launch_init_state(const Dev<T> &d, const T *c_in, const T *w_in, const uint8_t *util,
                        hipStream_t s);
 template <typename T>
@@ -149,6 +151,40 @@ void launch_bin_link(const Dev<T> &d, int mode, hipStream_t s);
 template <typename T>
 void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s);
 void binned_configure();
+
+// Batched solve (pmp_batch.hip): many instances concatenated block-diagonally
+// into one global pattern, iterated together by one persistent kernel with
+// per-instance rho, residuals, stop flags and iteration counters.
+template <typename T>
+struct BDev {
+    Dev<T> g;                  // concatenated arrays; CSR/CSC with global indices
+    int B;                     // instances
+    const int *link_off;       // [B+1]
+    const int *stream_off;     // [B+1]
+    const double *lo, *hi;     // [B] boxes
+    Ctl *ictl;                 // [B] per-instance control blocks
+    HistEntry *hist;           // [B * kHist]
+    int nst, nlt;              // stream / link tiles (never straddle instances)
+    const int *st_seg;         // [nst+1] first stream of each tile
+    const int *st_inst;        // [nst]
+    const int *lt_seg;         // [nlt+1]
+    const int *lt_inst;        // [nlt]
+    const int *inst_st;        // [B+1] first stream tile of each instance
+    const int *inst_lt;        // [B+1] first link tile of each instance
+    double *st_part;           // [nst]
+    double *lt_part;           // [2 nlt]
+    unsigned *bar;             // [2] grid barrier: arrivals, generation
+    int *abort;                // set when a barrier wait exceeds its bound
+};
+
+template <typename T>
+void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int adapt_every,
+                  hipStream_t s);
+template <typename T>
+int batch_grid_size(int device);
+
+// Error text for the C ABI (pmp_api.hip).
+pmp_status set_error(pmp_status s, const char *fmt, ...);
 
 // Adjoint launchers (pmp_adjoint.hip).
 template <typename T>

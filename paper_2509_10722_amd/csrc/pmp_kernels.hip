@@ -160,6 +160,24 @@ __global__ void k_init_state(Dev<T> d, const T *c_in, const T *w_in, const uint8
 }
 
 template <typename T>
+__global__ void k_zero_state(Dev<T> d)
+{
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
+        d.a[j] = T(0);
+        d.x[j] = T(0);
+    }
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
+        d.b[l] = T(0);
+        d.zs[l] = T(0);
+        d.u[l] = T(0);
+        d.v[l] = T(0);
+        d.y_prev[l] = 0.0;
+        d.ps_prev[l] = 0.0;
+    }
+}
+
+template <typename T>
 __global__ void k_check_vectors(const T *c, const T *w, const uint8_t *util, int m, int n,
                                 Ctl *ctl)
 {
@@ -450,6 +468,13 @@ void launch_init_state(const Dev<T> &d, const T *c_in, const T *w_in, const uint
 }
 
 template <typename T>
+void launch_zero_state(const Dev<T> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_zero_state<T>), dim3(grid_for(d.n > d.m ? d.n : d.m, kBlock, 16384)),
+                       dim3(kBlock), 0, s, d);
+}
+
+template <typename T>
 void launch_check_vectors(const T *c, const T *w, const uint8_t *util, int m, int n, Ctl *ctl,
                           hipStream_t s)
 {
@@ -548,6 +573,7 @@ void launch_fill_int(int *p, int value, size_t count, hipStream_t s)
                                            hipStream_t);                                    \
     template void launch_rescale<T>(const Dev<T> &, hipStream_t);                           \
     template void launch_refresh_v<T>(const Dev<T> &, hipStream_t);                         \
+    template void launch_zero_state<T>(const Dev<T> &, hipStream_t);                        \
     template void launch_init_state<T>(const Dev<T> &, const T *, const T *,               \
                                        const uint8_t *, hipStream_t);                       \
     template void launch_check_vectors<T>(const T *, const T *, const uint8_t *, int, int, \

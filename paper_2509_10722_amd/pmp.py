@@ -350,3 +350,111 @@ def pmp_objective(c, w, solver, K, s=25):
     if _PMPFunction is None:
         _PMPFunction = _autograd_function()
     return _PMPFunction.apply(c, w, solver, K, s)
+
+
+class pmp_batch_options(ctypes.Structure):
+    _fields_ = [("class_m", ctypes.c_int32 * 2), ("tile_cap", ctypes.c_int32 * 3)]
+
+
+_BATCH_SIGNATURES = {
+    "pmp_batch_options_default": [ctypes.POINTER(pmp_batch_options)],
+    "pmp_batch_workspace_size": [ctypes.c_int32, ctypes.POINTER(pmp_problem),
+                                 ctypes.POINTER(pmp_params), ctypes.POINTER(pmp_batch_options),
+                                 ctypes.POINTER(ctypes.c_size_t)],
+    "pmp_batch_setup": [ctypes.c_int32, ctypes.POINTER(pmp_problem), ctypes.POINTER(pmp_params),
+                        ctypes.POINTER(pmp_batch_options), _P, ctypes.c_size_t, _P,
+                        ctypes.POINTER(_P)],
+    "pmp_batch_solve": [_P, ctypes.c_int32, ctypes.POINTER(pmp_result)],
+    "pmp_batch_get_solution": [_P, ctypes.c_int32, _P, _P, _P],
+    "pmp_batch_reset": [_P],
+    "pmp_batch_destroy": [_P],
+}
+_SIGNATURES.update(_BATCH_SIGNATURES)
+
+
+def batch_options_default(**caps) -> pmp_batch_options:
+    o = pmp_batch_options()
+    _check(load_library().pmp_batch_options_default(ctypes.byref(o)), "pmp_batch_options_default")
+    if "tile_cap" in caps:
+        for i, v in enumerate(caps["tile_cap"]):
+            o.tile_cap[i] = int(v)
+    if "class_m" in caps:
+        for i, v in enumerate(caps["class_m"]):
+            o.class_m[i] = int(v)
+    return o
+
+
+class BatchSolver:
+    """Many instances solved together by one persistent kernel launch per
+    solve (pmp_batch_*).  Instances are host-resident Instance objects."""
+
+    def __init__(self, insts, dtype=None, params=None, options=None, device="cuda", **kw):
+        import torch
+        lib = load_library()
+        self.torch = torch
+        self.lib = lib
+        self.dtype = dtype or torch.float32
+        self.device = torch.device(device)
+        npdt = np.float32 if self.dtype == torch.float32 else np.float64
+        dt = PMP_F32 if self.dtype == torch.float32 else PMP_F64
+        self.params = params or params_default(**kw)
+        self.options = options or batch_options_default()
+        self.count = len(insts)
+        self.sizes = [(int(i.m), int(i.n)) for i in insts]
+        keep = []
+        probs = (pmp_problem * self.count)()
+        for k, inst in enumerate(insts):
+            arrs = [np.ascontiguousarray(inst.row_ptr, dtype=np.int32),
+                    np.ascontiguousarray(inst.col_idx, dtype=np.int32),
+                    np.ascontiguousarray(inst.c, dtype=npdt),
+                    np.ascontiguousarray(inst.w, dtype=npdt),
+                    np.ascontiguousarray(inst.utility, dtype=np.uint8)]
+            keep.append(arrs)
+            probs[k] = pmp_problem(int(inst.m), int(inst.n), int(inst.row_ptr[-1]),
+                                   *[a.ctypes.data for a in arrs], float(inst.lo), float(inst.hi),
+                                   dt, PMP_MEM_HOST)
+        nbytes = ctypes.c_size_t()
+        _check(lib.pmp_batch_workspace_size(self.count, probs, ctypes.byref(self.params),
+                                            ctypes.byref(self.options), ctypes.byref(nbytes)),
+               "pmp_batch_workspace_size")
+        self.workspace = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.pmp_batch_setup(self.count, probs, ctypes.byref(self.params),
+                                   ctypes.byref(self.options), self.workspace.data_ptr(),
+                                   nbytes.value, self.stream.cuda_stream, ctypes.byref(h)),
+               "pmp_batch_setup")
+        self.handle = h
+        del keep
+
+    def solve(self, max_iter):
+        res = (pmp_result * self.count)()
+        st = self.lib.pmp_batch_solve(self.handle, int(max_iter), res)
+        _check(st, "pmp_batch_solve", allow=(PMP_OK, PMP_NOT_CONVERGED))
+        return [{"iterations": r.iterations, "r_norm": r.r_norm, "s_norm": r.s_norm,
+                 "eps_tol": r.eps_tol, "rho": r.rho, "converged": r.status == PMP_OK}
+                for r in res]
+
+    def solution(self, k):
+        m, n = self.sizes[k]
+        t = self.torch
+        x = t.empty(max(n, 1), dtype=self.dtype, device=self.device)
+        lam = t.empty(m, dtype=self.dtype, device=self.device)
+        slack = t.empty(m, dtype=self.dtype, device=self.device)
+        _check(self.lib.pmp_batch_get_solution(self.handle, int(k), x.data_ptr(), lam.data_ptr(),
+                                               slack.data_ptr()), "pmp_batch_get_solution")
+        return x[:n], lam, slack
+
+    def reset(self):
+        _check(self.lib.pmp_batch_reset(self.handle), "pmp_batch_reset")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pmp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

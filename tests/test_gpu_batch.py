@@ -1,0 +1,94 @@
+"""Batched persistent solves (pmp_batch_*) against plain solves and the
+oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_10722_amd import instances as I
+from tests.gpu_util import host, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2509_10722_amd.pmp import BatchSolver, Solver, batch_options_default  # noqa: E402
+
+
+def _small_batch(count=6, scale=0.01, seed=3):
+    return I.batched(seed=seed, count=count, scale=scale)
+
+
+def test_batch_matches_plain_solves_fp64():
+    insts = _small_batch()
+    b = BatchSolver(insts, dtype=torch.float64)
+    res = b.solve(20000)
+    for k, inst in enumerate(insts):
+        s = Solver(inst, dtype=torch.float64)
+        r = s.solve()
+        x, lam, _ = s.solution()
+        xb, lb, _ = b.solution(k)
+        print(f"instance {k} (m={inst.m}): batch {res[k]['iterations']} it, plain {r['iterations']} it")
+        assert res[k]["converged"] and r["converged"]
+        assert res[k]["iterations"] == r["iterations"]
+        assert torch.equal(x, xb) and torch.equal(lam, lb)
+        s.close()
+    b.close()
+
+
+def test_batch_fp32_equal_iterations_vs_oracle():
+    insts = [i.rounded(np.float32) for i in _small_batch(count=4)]
+    K = 120
+    b = BatchSolver(insts, dtype=torch.float32, eps_abs=0.0)
+    res = b.solve(K)
+    for k, inst in enumerate(insts):
+        assert res[k]["iterations"] == K and not res[k]["converged"]
+        o = oracle.run(inst, K)
+        x, lam, _ = b.solution(k)
+        assert rel(host(x), o["x"]) <= 1e-5 and rel(host(lam), o["lam"]) <= 1e-5
+    b.close()
+
+
+def test_tile_caps_do_not_change_iterates():
+    insts = _small_batch(count=5)
+    outs = []
+    for caps in ((64, 64, 64), (4096, 4096, 4096), (512, 1024, 2048)):
+        b = BatchSolver(insts, dtype=torch.float64, eps_abs=0.0,
+                        options=batch_options_default(tile_cap=caps))
+        b.solve(90)
+        outs.append([host(b.solution(k)[0]) for k in range(len(insts))])
+        b.close()
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            assert np.array_equal(a, c)
+
+
+def test_batch_reset_and_continue():
+    insts = _small_batch(count=3)
+    b = BatchSolver(insts, dtype=torch.float64, eps_abs=0.0)
+    b.solve(50)
+    b.solve(30)
+    x1 = [host(b.solution(k)[0]) for k in range(3)]
+    b.reset()
+    b.solve(80)
+    x2 = [host(b.solution(k)[0]) for k in range(3)]
+    for a, c in zip(x1, x2):
+        assert np.array_equal(a, c)
+    b.close()
+
+
+def test_batch_mixed_sizes_with_degenerate_instance():
+    rng = np.random.default_rng(0)
+    insts = [I.paper_example(1.0, 3.0, hi=50.0), I.tiny(), I.transit_instance(rng, 500),
+             I.single_link([1.0, 2.0], [0, 1], 4.0, hi=50.0)]
+    for i in insts:
+        i.lo, i.hi = 0.0, 50.0
+    b = BatchSolver(insts, dtype=torch.float64)
+    res = b.solve(20000)
+    for k, inst in enumerate(insts):
+        o = oracle.run(inst, 100000, stop=True)
+        xb, _, _ = b.solution(k)
+        assert res[k]["converged"] and res[k]["iterations"] == o["iterations"]
+        assert rel(host(xb), o["x"]) <= 1e-10
+    b.close()
