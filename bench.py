@@ -61,6 +61,116 @@ def load_traffic(kernel, layout, workload):
     return t.get("bytes_per_launch")
 
 
+def bench_batched(args, log):
+    """Pattern 2: the batched transit workload (64 instances, m log-uniform
+    on [1e3, 1e5], n = 5m, degraded capacities) solved to the 1e-4 rule by
+    one persistent launch, against solving the instances one by one."""
+    import numpy as np
+    import torch
+
+    from paper_2509_10722_amd import autotune, instances
+    from paper_2509_10722_amd.pmp import BatchSolver, Solver
+
+    insts = [i.rounded(np.float32) for i in instances.batched(scale=args.scale)]
+    tot = {"m": sum(i.m for i in insts), "n": sum(i.n for i in insts),
+           "nnz": sum(i.nnz for i in insts)}
+    log(f"[bench] batched: {len(insts)} instances, {tot}")
+    if args.tune:
+        opts, timings = autotune.tune_batch(insts, dtype=torch.float32, log=log)
+    else:
+        opts = autotune.cached_options(torch)
+    caps = list(opts.tile_cap)
+    b = BatchSolver(insts, dtype=torch.float32, options=opts)
+    b.solve(20)                     # warm-up: graph capture, first touch
+    b.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = b.solve(args.tol_max_iter)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    b.close()
+    iters = [r["iterations"] for r in res]
+    conv = sum(r["converged"] for r in res)
+    log(f"[bench] batched solve: {tb:.3f} s, {conv}/{len(insts)} converged, "
+        f"iterations {min(iters)}..{max(iters)}")
+    # the same instances one by one (graph-replayed pmp_solve each)
+    tp = 0.0
+    plain_iters = []
+    for inst in insts:
+        s = Solver(inst, dtype=torch.float32, max_iter=args.tol_max_iter)
+        s.solve()
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t0
+        plain_iters.append(r["iterations"])
+        s.close()
+    work = sum(bytes_model(i.n, i.m, i.nnz)["iteration"] * k for i, k in zip(insts, iters))
+    line = {
+        "metric": "batched PMP instance-iterations/sec (64 transit instances, to 1e-4)",
+        "value": round(sum(iters) / tb, 1), "unit": "instance-iter/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched transit x{len(insts)}", **tot, "tile_cap": caps},
+        "time_s": round(tb, 4), "plain_time_s": round(tp, 4),
+        "speedup_vs_plain": round(tp / tb, 3), "converged": conv,
+        "iterations_equal_plain": sum(int(a == c) for a, c in zip(iters, plain_iters)),
+        "model_gbs": round(work / tb / 1e9, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_adjoint(args, log):
+    """Pattern 3: gradient of sum_j w_j log x_j^K (K = 500, checkpoints every
+    25) with respect to c and w on the adjoint workload, against K plain
+    iterations."""
+    import numpy as np
+    import torch
+
+    from paper_2509_10722_amd import instances
+    from paper_2509_10722_amd.pmp import Solver
+
+    inst = instances.adjoint(scale=args.scale).rounded(np.float32)
+    K, s = 500, 25
+    solver = Solver(inst, dtype=torch.float32, adapt_every=0)
+    solver.iterate(K)
+    solver.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.iterate(K)
+    solver.residuals()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    solver.reset()
+    solver.forward_ckpt(K, s)
+    solver.backward()
+    solver.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = solver.forward_ckpt(K, s)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gc, gw = solver.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    solver.close()
+    line = {
+        "metric": "PMP reverse mode: seconds per gradient (K=500 unrolled iterations)",
+        "value": round(t_fwd + t_bwd, 4), "unit": "s", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"adjoint (m={inst.m}, n={inst.n}, nnz={inst.nnz})", "K": K,
+                   "checkpoint_every": s},
+        "forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
+        "plain_K_iterations_s": round(t_plain, 4),
+        "ratio_vs_plain": round((t_fwd + t_bwd) / t_plain, 3), "J": J,
+        "grad_c_norm": float(torch.linalg.vector_norm(gc.double())),
+        "grad_w_norm": float(torch.linalg.vector_norm(gw.double())),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +184,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "gather", "binned"])
+    ap.add_argument("--pattern", default="plain", choices=["plain", "batched", "adjoint"],
+                    help="plain: the large workload (the default line); batched / adjoint: "
+                         "the two training-system patterns, one JSON line each")
+    ap.add_argument("--tune", action="store_true", help="batched: run the tile autotuner first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -92,6 +206,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.pattern == "batched":
+        return bench_batched(args, log)
+    if args.pattern == "adjoint":
+        return bench_adjoint(args, log)
 
     if args.calibrate_copy:
         # an elementwise kernel that reads and writes 1 GiB each (known bytes)

@@ -103,12 +103,13 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
     L.util = take((size_t)n);
     if (L.binned) {
         const size_t tiles = (size_t)L.bp.P * (size_t)L.bp.Q + 1;
-        L.mx = take((size_t)nnz * sz);
-        L.mv = take((size_t)nnz * sz);
-        L.lix = take((size_t)nnz * 2);
-        L.six = take((size_t)nnz * 2);
-        L.ox = take(tiles * 8);
-        L.ov = take(tiles * 8);
+        // 4 entries of padding: the accumulation reads aligned groups of 4
+        L.mx = take((size_t)(nnz + 4) * sz);
+        L.mv = take((size_t)(nnz + 4) * sz);
+        L.lix = take((size_t)(nnz + 4) * 2);
+        L.six = take((size_t)(nnz + 4) * 2);
+        L.ox = take(tiles * 4);
+        L.ov = take(tiles * 4);
     }
     L.total = off;
     return L;
@@ -325,18 +326,18 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         d.mv = (T *)(ws + L.mv);
         d.lix = (const uint16_t *)(ws + L.lix);
         d.six = (const uint16_t *)(ws + L.six);
-        d.ox = (const long long *)(ws + L.ox);
-        d.ov = (const long long *)(ws + L.ov);
+        d.ox = (const int *)(ws + L.ox);
+        d.ov = (const int *)(ws + L.ov);
         const size_t tiles = (size_t)d.P * (size_t)d.Q + 1;
         std::vector<int> hcolidx((size_t)nnz);
         if (nnz) HIP_TRY(hipMemcpyAsync(hcolidx.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        std::vector<long long> ox(tiles), ov(tiles);
+        std::vector<int> ox(tiles), ov(tiles);
         std::vector<uint16_t> lix((size_t)nnz), six((size_t)nnz);
         binned_build_host(hrow.data(), hcolidx.data(), m, n, L.bp, ox.data(), ov.data(), lix.data(),
                           six.data());
-        HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 8, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 8, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 4, hipMemcpyHostToDevice, s));
         if (nnz) {
             HIP_TRY(hipMemcpyAsync((void *)d.lix, lix.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
             HIP_TRY(hipMemcpyAsync((void *)d.six, six.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
@@ -350,11 +351,13 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
 }
 
 // One pass of either layout.
+// The stream pass; mode as for the link pass (the gather layout always
+// stores x, the binned one only before and at checks).
 template <typename T>
-void stream_pass(const Dev<T> &d, bool check, hipStream_t s)
+void stream_pass(const Dev<T> &d, int mode, hipStream_t s)
 {
-    if (d.binned) launch_bin_stream<T>(d, check, s);
-    else launch_stream_pass<T>(d, check, s);
+    if (d.binned) launch_bin_stream<T>(d, mode, s);
+    else launch_stream_pass<T>(d, mode == kCheck, s);
 }
 
 // The link pass; a check also reduces its residual partials and decides
@@ -396,8 +399,8 @@ void enqueue_iterations(pmp_handle *h, int k, hipStream_t s)
         const long long it = h->iter_enq + 1;
         const bool check = i == k || (adapt > 0 && it % adapt == 0);
         const bool next_check = i < k && (i + 1 == k || (adapt > 0 && (it + 1) % adapt == 0));
-        stream_pass<T>(d, check, s);
         const int mode = check ? kCheck : (next_check ? kSave : kPlain);
+        stream_pass<T>(d, mode, s);
         link_pass<T>(d, mode, it - h->iter_fin, 0, s);
         if (check) {
             h->iter_fin = it;
@@ -416,8 +419,8 @@ pmp_status build_graph(pmp_handle *h)
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 1; i <= ce; ++i) {
         const bool check = i == ce;
-        stream_pass<T>(d, check, h->cap_stream);
         const int mode = check ? kCheck : (i == ce - 1 ? kSave : kPlain);
+        stream_pass<T>(d, mode, h->cap_stream);
         link_pass<T>(d, mode, ce, 1, h->cap_stream);
     }
     if (d.binned) launch_bin_emit<T>(d, 1, h->cap_stream);
@@ -576,6 +579,7 @@ pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
     hipStream_t st = h->stream;
     pmp_status rc;
     launch_ctl_clear_done(h->ctl, st);
+    launch_refresh_v<T>(d, st);   // the binned layout keeps v in its messages between checks
     for (int t = 1; t <= K; ++t) {
         if ((t - 1) % s == 0)
             if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)((t - 1) / s) * L.state, true)) != PMP_OK)
@@ -715,10 +719,11 @@ pmp_status time_kernels_impl(pmp_handle *h, int k, double *ms)
         const bool check = i == k || (adapt > 0 && it % adapt == 0);
         const bool next_check = i < k && (i + 1 == k || (adapt > 0 && (it + 1) % adapt == 0));
         is_check[i - 1] = check;
+        const int mode = check ? kCheck : (next_check ? kSave : kPlain);
         (void)hipEventRecord(ev[3 * (i - 1)], s);
-        stream_pass<T>(d, check, s);
+        stream_pass<T>(d, mode, s);
         (void)hipEventRecord(ev[3 * (i - 1) + 1], s);
-        link_pass<T>(d, check ? kCheck : (next_check ? kSave : kPlain), it - h->iter_fin, 0, s);
+        link_pass<T>(d, mode, it - h->iter_fin, 0, s);
         if (check) {
             h->iter_fin = it;
             after_check<T>(d, adapt > 0 && it % adapt == 0, s);

@@ -45,7 +45,7 @@ BinnedPlan binned_plan(int m, int n)
 }
 
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
-                       long long *ox, long long *ov, uint16_t *lix, uint16_t *six)
+                       int *ox, int *ov, uint16_t *lix, uint16_t *six)
 {
     const long long P = bp.P, Q = bp.Q;
     std::vector<long long> cnt((size_t)(P * Q), 0);
@@ -53,20 +53,20 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
         const long long p = l / bp.LB;
         for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) cnt[(size_t)(p * Q + col_idx[k] / bp.SB)]++;
     }
-    long long acc = 0;
+    long long acc = 0;   // < nnz < 2^31
     for (long long p = 0; p < P; ++p)
         for (long long q = 0; q < Q; ++q) {
-            ox[p * Q + q] = acc;
+            ox[p * Q + q] = (int)acc;
             acc += cnt[(size_t)(p * Q + q)];
         }
-    ox[P * Q] = acc;
+    ox[P * Q] = (int)acc;
     acc = 0;
     for (long long q = 0; q < Q; ++q)
         for (long long p = 0; p < P; ++p) {
-            ov[q * P + p] = acc;
+            ov[q * P + p] = (int)acc;
             acc += cnt[(size_t)(p * Q + q)];
         }
-    ov[Q * P] = acc;
+    ov[Q * P] = (int)acc;
     std::fill(cnt.begin(), cnt.end(), 0);
     for (int l = 0; l < m; ++l) {
         const long long p = l / bp.LB;
@@ -82,7 +82,66 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
 
 namespace {
 
-template <typename T, bool CHECK>
+// Add messages msg[e0..e1) into acc[idx[e]] (FP64 LDS atomics).  FP32
+// messages are read four at a time (16-byte message and 8-byte index loads,
+// aligned; the arrays carry 4 entries of padding), entries outside
+// [e0, e1) being masked.
+template <typename T>
+__device__ __forceinline__ void accumulate(const T *__restrict__ msg,
+                                           const uint16_t *__restrict__ idx, int e0, int e1,
+                                           double *acc)
+{
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        typedef unsigned short u4 __attribute__((ext_vector_type(4)));
+        const f4 *m4 = (const f4 *)msg;
+        const u4 *i4 = (const u4 *)idx;
+        for (int b = (e0 >> 2) + threadIdx.x; b < ((e1 + 3) >> 2); b += kBinThreads) {
+            const f4 v = __builtin_nontemporal_load(m4 + b);
+            const u4 k = __builtin_nontemporal_load(i4 + b);
+            const int e = b << 2;
+            if (e >= e0 && e < e1) unsafeAtomicAdd(&acc[k.x], (double)v.x);
+            if (e + 1 >= e0 && e + 1 < e1) unsafeAtomicAdd(&acc[k.y], (double)v.y);
+            if (e + 2 >= e0 && e + 2 < e1) unsafeAtomicAdd(&acc[k.z], (double)v.z);
+            if (e + 3 >= e0 && e + 3 < e1) unsafeAtomicAdd(&acc[k.w], (double)v.w);
+        }
+    } else {
+        for (int e = e0 + threadIdx.x; e < e1; e += kBinThreads)
+            unsafeAtomicAdd(&acc[idx[e]], (double)__builtin_nontemporal_load(msg + e));
+    }
+}
+
+// Write the messages of one workgroup's tiles.  Lane i of a wave first loads
+// the offsets of the i-th tile of the wave's next 64 tiles, so the 64 tiles'
+// offset loads overlap; the wave then walks the tiles, taking each tile's
+// offsets from the owning lane and writing the tile with all 64 lanes.
+//   src_off[t], src_off[t + 1]   tile t in the read layout (index array idx)
+//   dst_off[t * dst_stride]      tile t in the written layout
+template <typename T>
+__device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
+                                           const int *__restrict__ dst_off, int dst_stride,
+                                           int ntiles, const uint16_t *__restrict__ idx,
+                                           const double *vals, T *__restrict__ out)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int kWaves = kBinThreads / 64;
+    for (int base = wave * 64; base < ntiles; base += kWaves * 64) {
+        const int t = base + lane;
+        int src = 0, cnt = 0, dst = 0;
+        if (t < ntiles) {
+            src = src_off[t];
+            cnt = src_off[t + 1] - src;
+            dst = dst_off[(long long)t * dst_stride];
+        }
+        const int nt = min(64, ntiles - base);
+        for (int i = 0; i < nt; ++i) {
+            const int s_i = __shfl(src, i, 64), c_i = __shfl(cnt, i, 64), d_i = __shfl(dst, i, 64);
+            for (int k = lane; k < c_i; k += 64) out[d_i + k] = (T)vals[idx[s_i + k]];
+        }
+    }
+}
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
 {
     if (d.ctl->done) return;
@@ -93,41 +152,31 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
     const int ns = min(d.SB, d.n - j0);
     for (int i = threadIdx.x; i < ns; i += kBinThreads) S[i] = 0.0;
     __syncthreads();
-    const long long e0 = d.ov[(long long)q * d.P], e1 = d.ov[(long long)(q + 1) * d.P];
-    for (long long e = e0 + threadIdx.x; e < e1; e += kBinThreads)
-        unsafeAtomicAdd(&S[d.six[e]], (double)__builtin_nontemporal_load(d.mv + e));
+    accumulate<T>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
     __syncthreads();
     const double rho = d.ctl->rho;
     double part = 0.0;
     for (int i = threadIdx.x; i < ns; i += kBinThreads) {
         const int j = j0 + i;
         const int L = d.col_ptr[j + 1] - d.col_ptr[j];
-        part += stream_update<T, CHECK>(d, j, L, S[i], rho);
-        S[i] = (double)d.x[j];
+        const double a = (double)d.a[j];
+        const T xt = (T)prox_stream((double)L * a + S[i], L, (double)d.wsig[j], rho, d.lo, d.hi);
+        const double xn = (double)xt;
+        if (MODE == kCheck) {                  // dual residual: sum_j L_j (dx_j)^2
+            const double dx = xn - (double)d.x[j];
+            part += (double)L * dx * dx;
+        }
+        if (MODE != kPlain) d.x[j] = xt;       // otherwise x travels only in the messages
+        d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
+        S[i] = xn;
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int p = wave; p < d.P; p += kBinThreads / 64) {
-        const long long src = d.ov[(long long)q * d.P + p];
-        const long long cnt = d.ov[(long long)q * d.P + p + 1] - src;
-        const long long dst = d.ox[(long long)p * d.Q + q];
-        for (long long k = lane; k < cnt; k += 64) d.mx[dst + k] = (T)S[d.six[src + k]];
-    }
-    if (CHECK) {
+    // tile (q, p) of the v messages and tile (p, q) of the x messages list the
+    // same nonzeros in the same order
+    emit_tiles<T>(d.ov + (long long)q * d.P, d.ox + q, d.Q, d.P, d.six, S, d.mx);
+    if (MODE == kCheck) {
         part = block_sum_n<kBinThreads>(part, sred);
         if (threadIdx.x == 0) d.spart[q] = part;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void emit_links(const Dev<T> &d, const double *Y, int p)
-{
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int q = wave; q < d.Q; q += kBinThreads / 64) {
-        const long long src = d.ox[(long long)p * d.Q + q];
-        const long long cnt = d.ox[(long long)p * d.Q + q + 1] - src;
-        const long long dst = d.ov[(long long)q * d.P + p];
-        for (long long k = lane; k < cnt; k += 64) d.mv[dst + k] = (T)Y[d.lix[src + k]];
     }
 }
 
@@ -142,21 +191,20 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_link(Dev<T> d)
     const int nl = min(d.LB, d.m - l0);
     for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = 0.0;
     __syncthreads();
-    const long long e0 = d.ox[(long long)p * d.Q], e1 = d.ox[(long long)(p + 1) * d.Q];
-    for (long long e = e0 + threadIdx.x; e < e1; e += kBinThreads)
-        unsafeAtomicAdd(&Y[d.lix[e]], (double)__builtin_nontemporal_load(d.mx + e));
+    accumulate<T>(d.mx, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
     __syncthreads();
     double r2 = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < nl; i += kBinThreads) {
         const int l = l0 + i;
-        link_update<T, MODE>(d, l, d.row_ptr[l + 1] - d.row_ptr[l], Y[i], r2, s2);
-        Y[i] = (double)d.v[l];
+        const int deg = d.row_ptr[l + 1] - d.row_ptr[l];
+        // v goes out in the messages; a check stores it for k_bin_emit
+        Y[i] = MODE == kCheck ? link_update<T, MODE, true>(d, l, deg, Y[i], r2, s2)
+                              : link_update<T, MODE, false>(d, l, deg, Y[i], r2, s2);
     }
     if (MODE != kCheck) {
         __syncthreads();
-        emit_links<T>(d, Y, p);
+        emit_tiles<T>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, d.mv);
     } else {
-        // v is emitted by k_bin_emit once the rho decision is known
         r2 = block_sum_n<kBinThreads>(r2, sred);
         s2 = block_sum_n<kBinThreads>(s2, sred);
         if (threadIdx.x == 0) {
@@ -190,7 +238,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_emit(Dev<T> d, int apply)
         Y[i] = (double)vt;
     }
     __syncthreads();
-    emit_links<T>(d, Y, p);
+    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, d.mv);
 }
 
 }  // namespace
@@ -199,10 +247,12 @@ void binned_configure()
 {
     const int bytes = kBinMaxBlock * (int)sizeof(double);
 #define PMP_BIN_ATTR(K) (void)hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, bytes)
-    PMP_BIN_ATTR((k_bin_stream<float, false>));
-    PMP_BIN_ATTR((k_bin_stream<float, true>));
-    PMP_BIN_ATTR((k_bin_stream<double, false>));
-    PMP_BIN_ATTR((k_bin_stream<double, true>));
+    PMP_BIN_ATTR((k_bin_stream<float, kPlain>));
+    PMP_BIN_ATTR((k_bin_stream<float, kSave>));
+    PMP_BIN_ATTR((k_bin_stream<float, kCheck>));
+    PMP_BIN_ATTR((k_bin_stream<double, kPlain>));
+    PMP_BIN_ATTR((k_bin_stream<double, kSave>));
+    PMP_BIN_ATTR((k_bin_stream<double, kCheck>));
     PMP_BIN_ATTR((k_bin_link<float, kPlain>));
     PMP_BIN_ATTR((k_bin_link<float, kSave>));
     PMP_BIN_ATTR((k_bin_link<float, kCheck>));
@@ -215,11 +265,20 @@ void binned_configure()
 }
 
 template <typename T>
-void launch_bin_stream(const Dev<T> &d, bool check, hipStream_t s)
+void launch_bin_stream(const Dev<T> &d, int mode, hipStream_t s)
 {
     const size_t lds = (size_t)d.SB * sizeof(double);
-    if (check) hipLaunchKernelGGL((k_bin_stream<T, true>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
-    else hipLaunchKernelGGL((k_bin_stream<T, false>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+    switch (mode) {
+    case kPlain:
+        hipLaunchKernelGGL((k_bin_stream<T, kPlain>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        break;
+    case kSave:
+        hipLaunchKernelGGL((k_bin_stream<T, kSave>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        break;
+    default:
+        hipLaunchKernelGGL((k_bin_stream<T, kCheck>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        break;
+    }
 }
 
 template <typename T>
@@ -246,8 +305,8 @@ void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s)
                        s, d, apply);
 }
 
-template void launch_bin_stream<float>(const Dev<float> &, bool, hipStream_t);
-template void launch_bin_stream<double>(const Dev<double> &, bool, hipStream_t);
+template void launch_bin_stream<float>(const Dev<float> &, int, hipStream_t);
+template void launch_bin_stream<double>(const Dev<double> &, int, hipStream_t);
 template void launch_bin_link<float>(const Dev<float> &, int, hipStream_t);
 template void launch_bin_link<double>(const Dev<double> &, int, hipStream_t);
 template void launch_bin_emit<float>(const Dev<float> &, int, hipStream_t);

@@ -99,8 +99,8 @@ __device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, d
     return part;
 }
 
-template <typename T, int MODE>
-__device__ __forceinline__ void link_update(const Dev<T> &d, int l, int deg, double y,
+template <typename T, int MODE, bool WRITE_V = true>
+__device__ __forceinline__ double link_update(const Dev<T> &d, int l, int deg, double y,
                                             double &r2, double &s2)
 {
     const double c = (double)d.c[l], u = (double)d.u[l];
@@ -114,7 +114,8 @@ __device__ __forceinline__ void link_update(const Dev<T> &d, int l, int deg, dou
     d.b[l] = bt;
     d.zs[l] = (T)(al * (ps - pbar) + (1.0 - al) * zs);
     d.u[l] = ut;
-    d.v[l] = (T)((double)bt - (double)ut);
+    const T vt = (T)((double)bt - (double)ut);
+    if (WRITE_V) d.v[l] = vt;
     if (MODE == kCheck) {
         // ||r||^2 = sum_l |l| pbar_l^2 and, with D the change since the
         // previous iteration, the link part of ||s||^2 / rho^2:
@@ -131,6 +132,7 @@ __device__ __forceinline__ void link_update(const Dev<T> &d, int l, int deg, dou
         d.y_prev[l] = y;
         d.ps_prev[l] = ps;
     }
+    return (double)vt;
 }
 
 // ---- residual reduction, stop rule and rho balancing ---------------------

@@ -92,8 +92,8 @@ struct Dev {
     T *mv;                          // [nnz] link -> stream messages, tiles q-major
     const uint16_t *lix;            // [nnz] local link of each mx entry
     const uint16_t *six;            // [nnz] local stream of each mv entry
-    const long long *ox;            // [P Q + 1] tile offsets in mx, p-major
-    const long long *ov;            // [Q P + 1] tile offsets in mv, q-major
+    const int *ox;                  // [P Q + 1] tile offsets in mx, p-major
+    const int *ov;                  // [Q P + 1] tile offsets in mv, q-major
 };
 
 // Adjoint (reverse-mode) vectors, all FP64, in the adjoint workspace.
@@ -143,9 +143,11 @@ struct BinnedPlan {
 BinnedPlan binned_plan(int m, int n);
 // Host construction of ox, ov, lix, six from the CSR pattern.
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
-                       long long *ox, long long *ov, uint16_t *lix, uint16_t *six);
+                       int *ox, int *ov, uint16_t *lix, uint16_t *six);
+// mode: kPlain (x stays in the messages), kSave (x also stored, for the
+// next iteration's check), kCheck (residual partials; x stored)
 template <typename T>
-void launch_bin_stream(const Dev<T> &d, bool check, hipStream_t s);
+void launch_bin_stream(const Dev<T> &d, int mode, hipStream_t s);
 template <typename T>
 void launch_bin_link(const Dev<T> &d, int mode, hipStream_t s);
 template <typename T>

@@ -1,0 +1,70 @@
+"""Full-size parity on the large workload (m=5e6, n=2e7, nnz~1.17e8) in the
+configuration bench.py times (FP32, automatic layout = binned).
+
+The FP64 oracle runs the same instance (FP32-rounded data) for a few
+iterations; x and the prices are compared normwise.  Properties that hold
+at any size are checked after more iterations: the link flow balance of the
+link-side copies and the agreement of the binned and gather layouts.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import optimality as opt
+from paper_2509_10722_amd import instances as I
+from tests.gpu_util import host, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2509_10722_amd.pmp import PMP_LAYOUT_GATHER, Solver  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def large():
+    return I.large().rounded(np.float32)
+
+
+def test_large_equal_iterations_vs_oracle(large):
+    K = 4                                   # includes a check (residuals) at the end
+    s = Solver(large, dtype=torch.float32)
+    assert s.layout_in_use() == "binned"
+    s.iterate(K)
+    r, sn, it = s.residuals()
+    x, lam, slack = s.solution()
+    g = (host(x), host(lam), host(slack))
+    s.close()
+    o = oracle.run(large, K)
+    ex, el = rel(g[0], o["x"]), rel(g[1], o["lam"])
+    print(f"large K={K}: x {ex:.2e} lambda {el:.2e} r {r:.6e} (oracle {o['r_norm']:.6e}) "
+          f"s {sn:.6e} (oracle {o['s_norm']:.6e})")
+    assert it == K
+    assert ex <= 1e-5 and el <= 1e-5 and rel(g[2], o["slack"]) <= 1e-5
+    assert abs(r - o["r_norm"]) <= 1e-4 * o["r_norm"]
+    assert abs(sn - o["s_norm"]) <= 1e-3 * o["s_norm"]
+
+
+def test_large_binned_vs_gather_and_flow_balance(large):
+    K = 60
+    outs = []
+    for layout in (0, PMP_LAYOUT_GATHER):
+        s = Solver(large, dtype=torch.float32, layout=layout)
+        s.iterate(K)
+        x, lam, _ = s.solution()
+        v = s.views()
+        outs.append((host(x), host(lam), s.residuals(),
+                     host(v["a"]), host(v["b"]), host(v["zs"])))
+        s.close()
+    (xb, lb, rb, a, b, zs), (xg, lg, rg, *_) = outs
+    print(f"binned vs gather after {K}: x {rel(xb, xg):.2e} lambda {rel(lb, lg):.2e}, "
+          f"equal fraction {np.mean(xb == xg):.6f}")
+    assert rel(xb, xg) <= 1e-6 and rel(lb, lg) <= 1e-6
+    # (R a)_l + d_l b_l + zs_l = 0 up to FP32 rounding of the stored a, b, zs
+    Ra = opt.csr_matvec(large, a)
+    d = np.diff(large.row_ptr)
+    resid = np.abs(Ra + d * b + zs)
+    scale = np.abs(Ra) + np.abs(d * b) + np.abs(zs) + 1e-30
+    assert np.quantile(resid / scale, 0.999) < 1e-5
