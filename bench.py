@@ -171,6 +171,118 @@ def bench_adjoint(args, log):
     print(json.dumps(line), flush=True)
 
 
+def _state_parts(solver, buf):
+    """Split a state buffer (a[n], b[m], zs[m], u[m], rho, iteration)."""
+    import numpy as np
+    raw = buf.cpu().numpy()
+    esz = 4 if solver.dtype == solver.torch.float32 else 8
+    dt = np.float32 if esz == 4 else np.float64
+    n, m = solver.n, solver.m
+    vec = raw[: (n + 3 * m) * esz].view(dt)
+    tail = raw[(n + 3 * m) * esz:]
+    return (vec[:n], vec[n:n + m], vec[n + m:n + 2 * m], vec[n + 2 * m:],
+            tail[:8].view(np.float64)[0], tail[8:16].view(np.int64)[0])
+
+
+def _state_buffer(solver, a, b, zs, u, rho):
+    import numpy as np
+    dt = np.float32 if solver.dtype == solver.torch.float32 else np.float64
+    vec = np.concatenate([a, b, zs, u]).astype(dt)
+    tail = np.concatenate([np.array([rho], np.float64).view(np.uint8),
+                           np.zeros(1, np.int64).view(np.uint8)])
+    raw = np.concatenate([vec.view(np.uint8), tail])
+    return solver.torch.from_numpy(raw).to(solver.device)
+
+
+def prune_instance(inst, failed_links):
+    """Section V-D's link failure: drop the failed links' rows and every
+    stream that uses one of them.  Returns (pruned instance, kept links,
+    kept streams)."""
+    import numpy as np
+
+    from paper_2509_10722_amd import instances
+    failed = np.zeros(inst.m, bool)
+    failed[failed_links] = True
+    rows = np.repeat(np.arange(inst.m), np.diff(inst.row_ptr))
+    dead = np.zeros(inst.n, bool)
+    dead[inst.col_idx[failed[rows]]] = True
+    keep_l = np.flatnonzero(~failed)
+    keep_s = np.flatnonzero(~dead)
+    new_s = -np.ones(inst.n, np.int64)
+    new_s[keep_s] = np.arange(keep_s.size)
+    new_l = -np.ones(inst.m, np.int64)
+    new_l[keep_l] = np.arange(keep_l.size)
+    sel = (~failed[rows]) & (~dead[inst.col_idx])
+    row_ptr, col_idx = instances.csr_from_pairs(keep_l.size, keep_s.size, new_l[rows[sel]],
+                                                new_s[inst.col_idx[sel]])
+    p = instances.Instance(inst.name + "_pruned", keep_l.size, keep_s.size, row_ptr, col_idx,
+                           inst.c[keep_l], inst.w[keep_s], inst.utility[keep_s], inst.lo, inst.hi)
+    return p, keep_l, keep_s
+
+
+def bench_warmstart(args, log):
+    """Section V-D: re-solve after capacity degradation (25% of links lose
+    50%) and after link failure (25% of links fail; pruned), cold versus warm
+    started from the previous solution."""
+    import numpy as np
+    import torch
+
+    from paper_2509_10722_amd import instances
+    from paper_2509_10722_amd.pmp import Solver
+
+    inst = instances.make(args.config, scale=args.scale).rounded(np.float32)
+    rng = np.random.default_rng(7)
+    out = {}
+
+    def timed_solve(s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    base = Solver(inst, dtype=torch.float32, max_iter=args.tol_max_iter)
+    r0, t_base = timed_solve(base)
+    log(f"[bench] base solve: {r0['iterations']} it, {t_base:.3f} s")
+    # degradation: warm = same handle with new capacities
+    c_new = (inst.c * np.where(rng.random(inst.m) < 0.25, 0.5, 1.0)).astype(np.float32)
+    st0 = base.get_state()
+    base.update_capacity(c_new)
+    rw, tw = timed_solve(base)
+    deg = instances.Instance(inst.name, inst.m, inst.n, inst.row_ptr, inst.col_idx,
+                             c_new.astype(np.float64), inst.w, inst.utility, inst.lo, inst.hi)
+    cold = Solver(deg, dtype=torch.float32, max_iter=args.tol_max_iter)
+    rc, tc = timed_solve(cold)
+    cold.close()
+    out["degradation"] = {"cold_iters": rc["iterations"], "warm_iters": rw["iterations"],
+                          "cold_s": round(tc, 4), "warm_s": round(tw, 4),
+                          "speedup": round(tc / tw, 3)}
+    log(f"[bench] degradation: {out['degradation']}")
+    # failure: prune, warm start from the base solution restricted to survivors
+    base.set_state(st0)
+    failed = np.flatnonzero(rng.random(inst.m) < 0.25)
+    pr, keep_l, keep_s = prune_instance(inst, failed)
+    a, b, zs, u, rho, _ = _state_parts(base, base.get_state())
+    base.close()
+    cold = Solver(pr, dtype=torch.float32, max_iter=args.tol_max_iter)
+    rc, tc = timed_solve(cold)
+    cold.reset()
+    cold.set_state(_state_buffer(cold, a[keep_s], b[keep_l], zs[keep_l], u[keep_l], rho))
+    rw, tw = timed_solve(cold)
+    cold.close()
+    out["failure"] = {"links_failed": int(failed.size), "m_pruned": pr.m, "n_pruned": pr.n,
+                      "cold_iters": rc["iterations"], "warm_iters": rw["iterations"],
+                      "cold_s": round(tc, 4), "warm_s": round(tw, 4),
+                      "speedup": round(tc / tw, 3)}
+    log(f"[bench] failure: {out['failure']}")
+    line = {"metric": "warm-start re-solve speedup to 1e-4 (Section V-D)",
+            "value": out["degradation"]["speedup"], "unit": "x", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{args.config} (m={inst.m}, n={inst.n}, nnz={inst.nnz})"},
+            **out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,7 +296,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "gather", "binned"])
-    ap.add_argument("--pattern", default="plain", choices=["plain", "batched", "adjoint"],
+    ap.add_argument("--pattern", default="plain",
+                    choices=["plain", "batched", "adjoint", "warmstart"],
                     help="plain: the large workload (the default line); batched / adjoint: "
                          "the two training-system patterns, one JSON line each")
     ap.add_argument("--tune", action="store_true", help="batched: run the tile autotuner first")
@@ -210,6 +323,8 @@ def main():
         return bench_batched(args, log)
     if args.pattern == "adjoint":
         return bench_adjoint(args, log)
+    if args.pattern == "warmstart":
+        return bench_warmstart(args, log)
 
     if args.calibrate_copy:
         # an elementwise kernel that reads and writes 1 GiB each (known bytes)

@@ -111,10 +111,11 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
     }
 }
 
-// Write the messages of one workgroup's tiles.  Lane i of a wave first loads
-// the offsets of the i-th tile of the wave's next 64 tiles, so the 64 tiles'
-// offset loads overlap; the wave then walks the tiles, taking each tile's
-// offsets from the owning lane and writing the tile with all 64 lanes.
+// Write the messages of one workgroup's tiles.  Wave w takes tiles
+// w, w + W, w + 2W, ... (W waves).  Lane i first loads the offsets of the
+// wave's i-th tile of the next 64, so those loads overlap; the wave then walks
+// the tiles, taking each tile's offsets from the owning lane and writing the
+// tile with all 64 lanes.
 //   src_off[t], src_off[t + 1]   tile t in the read layout (index array idx)
 //   dst_off[t * dst_stride]      tile t in the written layout
 template <typename T>
@@ -123,17 +124,18 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
                                            int ntiles, const uint16_t *__restrict__ idx,
                                            const double *vals, T *__restrict__ out)
 {
+    constexpr int W = kBinThreads / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    constexpr int kWaves = kBinThreads / 64;
-    for (int base = wave * 64; base < ntiles; base += kWaves * 64) {
-        const int t = base + lane;
+    const int mine = ntiles > wave ? (ntiles - wave + W - 1) / W : 0;   // tiles of this wave
+    for (int base = 0; base < mine; base += 64) {
+        const int t = wave + (base + lane) * W;
         int src = 0, cnt = 0, dst = 0;
-        if (t < ntiles) {
+        if (base + lane < mine) {
             src = src_off[t];
             cnt = src_off[t + 1] - src;
             dst = dst_off[(long long)t * dst_stride];
         }
-        const int nt = min(64, ntiles - base);
+        const int nt = min(64, mine - base);
         for (int i = 0; i < nt; ++i) {
             const int s_i = __shfl(src, i, 64), c_i = __shfl(cnt, i, 64), d_i = __shfl(dst, i, 64);
             for (int k = lane; k < c_i; k += 64) out[d_i + k] = (T)vals[idx[s_i + k]];
