@@ -229,14 +229,22 @@ pmp_status pmp_backward(pmp_handle *h, void *grad_c, void *grad_w);
  * own rho, residuals, stop flag and iteration count (Section III-F/G applied
  * per instance), and stopped instances drop out of the work.  Workgroup tiles
  * never straddle instances; their nonzero limit (tile_cap, in [64, 4096]) is
- * set per instance size class: m < class_m[0], m < class_m[1], larger. */
+ * set per instance size class: m < class_m[0], m < class_m[1], larger.
+ * With reorder_streams = 1 each instance's streams are renumbered inside the
+ * library by the first link of their route (ties by index), which puts the
+ * streams of one link close together when routes are local (as in
+ * time-expanded transit networks) and so keeps the link gathers in cache;
+ * every sum keeps its order, so results are unchanged, and solutions are
+ * returned in the caller's numbering. */
 typedef struct pmp_batch pmp_batch;
 typedef struct {
     int32_t class_m[2];
     int32_t tile_cap[3];
+    int32_t reorder_streams;
 } pmp_batch_options;
 
-/* Defaults: classes at m = 1e4 and 5e4, tile caps 1024 / 2048 / 4096. */
+/* Defaults: classes at m = 1e4 and 5e4, tile caps 1024 / 2048 / 4096,
+ * reorder_streams 1. */
 pmp_status pmp_batch_options_default(pmp_batch_options *options);
 pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,
                                     const pmp_params *params, const pmp_batch_options *options,

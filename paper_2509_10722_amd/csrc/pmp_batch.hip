@@ -223,6 +223,23 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
 
 }  // namespace
 
+namespace {
+template <typename T>
+__global__ void k_gather_x(const T *x, const int *pos, int n, T *out)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        out[j] = x[pos[j]];
+}
+}  // namespace
+
+template <typename T>
+void launch_batch_gather_x(const T *x, const int *pos, int n, T *out, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int g = std::min(16384, (n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_gather_x<T>), dim3(g), dim3(kBlock), 0, s, x, pos, n, out);
+}
+
 template <typename T>
 void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int adapt_every,
                   hipStream_t s)
@@ -245,6 +262,8 @@ int batch_grid_size(int device)
     return std::min(per_cu, 4) * cus;
 }
 
+template void launch_batch_gather_x<float>(const float *, const int *, int, float *, hipStream_t);
+template void launch_batch_gather_x<double>(const double *, const int *, int, double *, hipStream_t);
 template void launch_batch<float>(const BDev<float> &, int, int, int, int, hipStream_t);
 template void launch_batch<double>(const BDev<double> &, int, int, int, int, hipStream_t);
 template int batch_grid_size<float>(int);
@@ -273,7 +292,7 @@ struct BatchSizes {
 struct BatchLayout {
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
     size_t link_off, stream_off, lo, hi, ictl, hist, st_seg, st_inst, lt_seg, lt_inst;
-    size_t inst_st, inst_lt, st_part, lt_part, bar, util, total;
+    size_t inst_st, inst_lt, st_part, lt_part, bar, util, sperm, total;
     long long nst_max, nlt_max;
 };
 
@@ -319,6 +338,7 @@ BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap)
     L.lt_part = take((size_t)L.nlt_max * 16);
     L.bar = take(16);
     L.util = take(N);
+    L.sperm = take(N * 4);
     L.total = off;
     return L;
 }
@@ -414,6 +434,7 @@ struct pmp_batch {
     std::vector<long long> nnz, iter_base;
     std::vector<double> eps_tol;
     int grid = 0;
+    int *sperm = nullptr;   // device: internal position of each caller stream
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_iters = -1;
@@ -467,18 +488,37 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     std::vector<double> lo((size_t)B), hi((size_t)B);
     b->link_off.assign((size_t)B + 1, 0);
     b->stream_off.assign((size_t)B + 1, 0);
+    std::vector<int> sperm((size_t)N);   // internal position of each caller stream
     long long eo = 0;
     for (int i = 0; i < B; ++i) {
         const pmp_problem &p = pr[i];
         const int lo_l = b->link_off[(size_t)i], lo_s = b->stream_off[(size_t)i];
+        // stream order: by the first link of the route, then by index
+        std::vector<int> newpos((size_t)p.n);
+        if (opt->reorder_streams) {
+            std::vector<int> first((size_t)p.n, p.m);
+            for (int l = p.m - 1; l >= 0; --l)
+                for (int k = p.row_ptr[l]; k < p.row_ptr[l + 1]; ++k) first[(size_t)p.col_idx[k]] = l;
+            std::vector<int> order((size_t)p.n);
+            for (int j = 0; j < p.n; ++j) order[(size_t)j] = j;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int x, int y) { return first[(size_t)x] < first[(size_t)y]; });
+            for (int r = 0; r < p.n; ++r) newpos[(size_t)order[(size_t)r]] = r;
+        } else {
+            for (int j = 0; j < p.n; ++j) newpos[(size_t)j] = j;
+        }
         for (int l = 0; l < p.m; ++l) {
             row_ptr[(size_t)lo_l + l] = (int)(eo + p.row_ptr[l]);
             c[(size_t)lo_l + l] = ((const T *)p.c)[l];
         }
-        for (long long k = 0; k < p.nnz; ++k) col_idx[(size_t)(eo + k)] = p.col_idx[k] + lo_s;
+        // entries keep their order inside each row, so every sum is unchanged
+        for (long long k = 0; k < p.nnz; ++k)
+            col_idx[(size_t)(eo + k)] = newpos[(size_t)p.col_idx[k]] + lo_s;
         for (int j = 0; j < p.n; ++j) {
-            w[(size_t)lo_s + j] = ((const T *)p.w)[j];
-            util[(size_t)lo_s + j] = p.utility[j];
+            const size_t t = (size_t)lo_s + newpos[(size_t)j];
+            w[t] = ((const T *)p.w)[j];
+            util[t] = p.utility[j];
+            sperm[(size_t)lo_s + j] = newpos[(size_t)j];
         }
         lo[(size_t)i] = p.lo;
         hi[(size_t)i] = p.hi;
@@ -532,6 +572,8 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     BATCH_TRY(hipMemcpyAsync((void *)d.link_off, b->link_off.data(), ((size_t)B + 1) * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.stream_off, b->stream_off.data(), ((size_t)B + 1) * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.lo, lo.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
+    b->sperm = (int *)(ws + L.sperm);
+    if (N) BATCH_TRY(hipMemcpyAsync(b->sperm, sperm.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.hi, hi.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
     launch_transpose(g.row_ptr, g.col_idx, M, N, E, (int *)g.col_ptr, (int *)g.row_idx, (int *)(ws + L.a), s);
     launch_init_state<T>(g, g.c, g.wsig, (const uint8_t *)(ws + L.util), s);
@@ -626,7 +668,8 @@ pmp_status batch_solution_impl(pmp_batch *b, int i, T *x, T *lambda, T *slack)
     di.c += l0;
     di.ps_prev += l0;
     di.ctl = d.ictl + i;
-    launch_solution<T>(di, x, lambda, slack, b->stream);
+    launch_solution<T>(di, nullptr, lambda, slack, b->stream);
+    if (x) launch_batch_gather_x<T>(d.g.x + s0, b->sperm + s0, b->n[(size_t)i], x, b->stream);
     BATCH_TRY(hipGetLastError());
     BATCH_TRY(hipStreamSynchronize(b->stream));
     return PMP_OK;
@@ -644,6 +687,7 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     o->tile_cap[0] = 1024;
     o->tile_cap[1] = 2048;
     o->tile_cap[2] = 4096;
+    o->reorder_streams = 1;
     return PMP_OK;
 }
 

@@ -184,6 +184,8 @@ void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int
                   hipStream_t s);
 template <typename T>
 int batch_grid_size(int device);
+template <typename T>
+void launch_batch_gather_x(const T *x, const int *pos, int n, T *out, hipStream_t s);
 
 // Error text for the C ABI (pmp_api.hip).
 pmp_status set_error(pmp_status s, const char *fmt, ...);

@@ -353,7 +353,8 @@ def pmp_objective(c, w, solver, K, s=25):
 
 
 class pmp_batch_options(ctypes.Structure):
-    _fields_ = [("class_m", ctypes.c_int32 * 2), ("tile_cap", ctypes.c_int32 * 3)]
+    _fields_ = [("class_m", ctypes.c_int32 * 2), ("tile_cap", ctypes.c_int32 * 3),
+                ("reorder_streams", ctypes.c_int32)]
 
 
 _BATCH_SIGNATURES = {
@@ -381,6 +382,8 @@ def batch_options_default(**caps) -> pmp_batch_options:
     if "class_m" in caps:
         for i, v in enumerate(caps["class_m"]):
             o.class_m[i] = int(v)
+    if "reorder_streams" in caps:
+        o.reorder_streams = int(caps["reorder_streams"])
     return o
 
 

@@ -92,3 +92,19 @@ def test_batch_mixed_sizes_with_degenerate_instance():
         assert res[k]["converged"] and res[k]["iterations"] == o["iterations"]
         assert rel(host(xb), o["x"]) <= 1e-10
     b.close()
+
+
+def test_stream_reordering_keeps_results():
+    """Renumbering streams by their first link changes only where they live
+    on the device, not any sum: results are identical and come back in the
+    caller's numbering."""
+    insts = _small_batch(count=4, seed=11)
+    outs = []
+    for reorder in (0, 1):
+        b = BatchSolver(insts, dtype=torch.float32, eps_abs=0.0,
+                        options=batch_options_default(reorder_streams=reorder))
+        b.solve(70)
+        outs.append([tuple(host(t) for t in b.solution(k)) for k in range(len(insts))])
+        b.close()
+    for (x0, l0, s0), (x1, l1, s1) in zip(*outs):
+        assert np.array_equal(x0, x1) and np.array_equal(l0, l1) and np.array_equal(s0, s1)
