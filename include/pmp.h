@@ -8,8 +8,8 @@
  *
  *   R  m x n link-route matrix with R_lj = 1 when stream j uses link l
  *      (eq. (1)); only its pattern is stored (CSR here, CSC built inside).
- *   U_j = w_j log x_j  (weighted proportional fairness) or  w_j x_j
- *      (linear), Section II.
+ *   U_j = w_j log x_j  (weighted proportional fairness),  w_j x_j
+ *      (linear), Section II, or  -w_j / x_j  (alpha = 2 fairness).
  *
  * Method: the over-relaxed PMP iteration of Section III-D..G (ADMM on the
  * terminal graph), held in a compact per-stream / per-link form:
@@ -59,7 +59,11 @@ typedef enum {
     PMP_ERR_STATE = 7       /* call not valid for this handle               */
 } pmp_status;
 
-typedef enum { PMP_UTIL_LOG = 0, PMP_UTIL_LINEAR = 1 } pmp_utility;
+/* Utilities (Section II): w log x (proportional fairness), w x (linear) and
+ * -w / x (minimum potential delay fairness, the alpha = 2 member of the
+ * alpha-fair family the paper names; its prox is the positive root of a
+ * cubic, found by Newton's method). */
+typedef enum { PMP_UTIL_LOG = 0, PMP_UTIL_LINEAR = 1, PMP_UTIL_ALPHA2 = 2 } pmp_utility;
 typedef enum { PMP_F32 = 0, PMP_F64 = 1 } pmp_dtype;
 typedef enum { PMP_MEM_HOST = 0, PMP_MEM_DEVICE = 1 } pmp_memory;
 

@@ -63,7 +63,7 @@ def _load():
         lib.orc_run.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)] + \
             [ctypes.c_void_p] * 9 + [ctypes.POINTER(_Result)]
-        for name in ("orc_prox_log", "orc_prox_linear"):
+        for name in ("orc_prox_log", "orc_prox_linear", "orc_prox_alpha2"):
             f = getattr(lib, name)
             f.restype = ctypes.c_double
             f.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_double,
@@ -84,6 +84,10 @@ def prox_log(S, L, w, rho, lo=0.0, hi=math.inf):
 
 def prox_linear(S, L, w, rho, lo=0.0, hi=math.inf):
     return _load().orc_prox_linear(S, L, w, rho, lo, hi)
+
+
+def prox_alpha2(S, L, w, rho, lo=0.0, hi=math.inf):
+    return _load().orc_prox_alpha2(S, L, w, rho, lo, hi)
 
 
 def prox_slack(zeta, c):

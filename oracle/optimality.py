@@ -4,7 +4,8 @@ These are exact statements about the optimum of
 
     maximize sum_j U_j(x_j)  s.t.  R x <= c,  lo <= x <= hi      (eq. (2) + box)
 
-with U_j(x) = w_j log x or w_j x (Section II), independent of how PMP reaches
+with U_j(x) = w_j log x, w_j x or -w_j / x (Section II's utilities and the
+alpha = 2 fairness it names), independent of how PMP reaches
 it.  They pin the iterative oracle (and, at convergence, the HIP solver):
 
   kkt_report        primal feasibility, dual feasibility, complementary
@@ -22,7 +23,7 @@ import math
 
 import numpy as np
 
-LOG, LINEAR = 0, 1
+LOG, LINEAR, ALPHA2 = 0, 1, 2
 
 
 def csr_matvec(inst, x):
@@ -40,27 +41,36 @@ def csr_rmatvec(inst, lam):
 
 
 def utility(inst, x):
-    """sum_j U_j(x_j); -inf if a log stream has x_j <= 0."""
+    """sum_j U_j(x_j); -inf if a log or alpha = 2 stream has x_j <= 0."""
     x = np.asarray(x, dtype=np.float64)
     log = inst.utility == LOG
-    if np.any(x[log] <= 0):
+    lin = inst.utility == LINEAR
+    a2 = inst.utility == ALPHA2
+    if np.any(x[log | a2] <= 0):
         return -math.inf
-    return float(np.sum(inst.w[log] * np.log(x[log])) + np.sum(inst.w[~log] * x[~log]))
+    return float(np.sum(inst.w[log] * np.log(x[log])) + np.sum(inst.w[lin] * x[lin])
+                 - np.sum(inst.w[a2] / x[a2]))
 
 
 def inner_max(inst, pi):
     """argmax and max over lo <= x <= hi of U_j(x) - pi_j x, per stream."""
     w, lo, hi = inst.w, inst.lo, inst.hi
     log = inst.utility == LOG
+    lin = inst.utility == LINEAR
+    a2 = inst.utility == ALPHA2
     xs = np.empty(inst.n)
+    safe = np.where(pi > 0, pi, 1.0)
     with np.errstate(divide="ignore", invalid="ignore"):
-        xl = np.where(pi > 0, np.clip(w / np.where(pi > 0, pi, 1.0), lo, hi), hi)
+        xl = np.where(pi > 0, np.clip(w / safe, lo, hi), hi)
+        xa = np.where(pi > 0, np.clip(np.sqrt(w / safe), lo, hi), hi)
     xs[log] = xl[log]
-    xs[~log] = np.where(w[~log] > pi[~log], hi, lo)
+    xs[a2] = xa[a2]
+    xs[lin] = np.where(w[lin] > pi[lin], hi, lo)
     val = np.empty(inst.n)
     with np.errstate(divide="ignore"):
         val[log] = w[log] * np.log(xs[log]) - pi[log] * xs[log]
-    val[~log] = (w[~log] - pi[~log]) * xs[~log]
+        val[a2] = -w[a2] / xs[a2] - pi[a2] * xs[a2]
+    val[lin] = (w[lin] - pi[lin]) * xs[lin]
     return xs, val
 
 
@@ -87,12 +97,15 @@ def kkt_report(inst, x, lam):
     scale = max(1.0, float(np.max(np.abs(lam_p * inst.c), initial=0.0)))
     rep["comp_slack"] = float(np.max(np.abs(lam_p * (inst.c - Rx)), initial=0.0) / scale)
     log = inst.utility == LOG
-    interior = log & (x > inst.lo + 1e-9 * max(1.0, inst.hi if math.isfinite(inst.hi) else 1.0)) \
+    a2 = inst.utility == ALPHA2
+    inner = (x > inst.lo + 1e-9 * max(1.0, inst.hi if math.isfinite(inst.hi) else 1.0)) \
         & (x < inst.hi * (1 - 1e-9))
+    interior = (log | a2) & inner
     if np.any(interior):
-        marg = inst.w[interior] / x[interior]
-        rep["stationarity_log"] = float(np.max(np.abs(marg - pi[interior]) /
-                                               np.maximum(marg, 1e-300)))
+        # marginal utility U'(x): w / x (log), w / x^2 (alpha = 2)
+        marg = np.where(log, inst.w / np.maximum(x, 1e-300), inst.w / np.maximum(x, 1e-300) ** 2)
+        rep["stationarity_log"] = float(np.max(np.abs(marg[interior] - pi[interior]) /
+                                               np.maximum(marg[interior], 1e-300)))
     else:
         rep["stationarity_log"] = 0.0
     # feasible point by uniform scaling (valid for lo = 0)
@@ -157,6 +170,14 @@ def single_link(w, util, cap, lo=0.0, hi=math.inf):
     return x, lam
 
 
+def single_link_alpha2(w, cap):
+    """One link, all alpha = 2 utilities -w_j / x_j, no binding box: KKT gives
+    w_j / x_j^2 = lam, so x_j = sqrt(w_j / lam) and sum_j x_j = cap:
+    x_j = cap sqrt(w_j) / sum_k sqrt(w_k), lam = (sum_k sqrt(w_k) / cap)^2."""
+    rw = np.sqrt(np.asarray(w, dtype=np.float64))
+    return cap * rw / rw.sum(), (rw.sum() / cap) ** 2
+
+
 def paper_example(c1, c):
     """Section III-A's network, all w = 1 log utilities, capacities
     (c1, c, c).  Link 1 carries stream 1 only; links 2 and 3 are symmetric and
@@ -171,27 +192,31 @@ def paper_example(c1, c):
 def brute_force(inst, x0=None):
     """SciPy FP64 optimum of a very small instance.
 
-    Primal: SLSQP on -U(x) with R x <= c and the box (log rates kept
-    positive).  Dual (all-log instances only): L-BFGS-B on D(lambda),
-    lambda >= 0.  Returns dict(primal_obj, x, dual_obj, lam)."""
+    Primal: SLSQP on -U(x) with R x <= c and the box (log and alpha = 2
+    rates kept positive).  Dual (instances without linear streams): L-BFGS-B
+    on D(lambda), lambda >= 0.  Returns dict(primal_obj, x, dual_obj, lam)."""
     from scipy.optimize import minimize
 
     R = np.zeros((inst.m, inst.n))
     rows = np.repeat(np.arange(inst.m), np.diff(inst.row_ptr))
     R[rows, inst.col_idx] = 1.0
     log = inst.utility == LOG
+    lin = inst.utility == LINEAR
+    a2 = inst.utility == ALPHA2
     hi = inst.hi if math.isfinite(inst.hi) else float(np.max(inst.c)) * 2
-    lo_b = np.where(log, max(inst.lo, 1e-9), inst.lo)
+    lo_b = np.where(log | a2, max(inst.lo, 1e-9), inst.lo)
     if x0 is None:
         x0 = np.full(inst.n, min(hi, float(np.min(inst.c))) / (inst.n + 1))
 
     def f(x):
-        return -(np.sum(inst.w[log] * np.log(x[log])) + np.sum(inst.w[~log] * x[~log]))
+        return -(np.sum(inst.w[log] * np.log(x[log])) + np.sum(inst.w[lin] * x[lin])
+                 - np.sum(inst.w[a2] / x[a2]))
 
     def g(x):
         gr = np.empty_like(x)
         gr[log] = -inst.w[log] / x[log]
-        gr[~log] = -inst.w[~log]
+        gr[lin] = -inst.w[lin]
+        gr[a2] = -inst.w[a2] / x[a2] ** 2
         return gr
 
     cons = [{"type": "ineq", "fun": lambda x: inst.c - R @ x, "jac": lambda x: -R}]
@@ -199,7 +224,7 @@ def brute_force(inst, x0=None):
                    constraints=cons, method="SLSQP",
                    options={"ftol": 1e-15, "maxiter": 2000})
     out = {"primal_obj": -float(res.fun), "x": res.x}
-    if np.all(log):
+    if not np.any(lin):          # D is continuously differentiable without linear streams
         def D(lam):
             return dual_value(inst, lam)
 

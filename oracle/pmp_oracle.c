@@ -65,7 +65,7 @@ typedef struct {
     const int32_t *col_idx;   /* [nnz] streams using each link             */
     const double *c;          /* [m] link capacities, > 0                  */
     const double *w;          /* [n] stream weights, > 0                   */
-    const uint8_t *utility;   /* [n] 0 = w log x, 1 = w x                  */
+    const uint8_t *utility;   /* [n] 0 = w log x, 1 = w x, 2 = -w / x      */
     double lo, hi;            /* box on every rate                         */
 } orc_problem;
 
@@ -106,6 +106,29 @@ double orc_prox_linear(double S, int64_t L, double w, double rho, double lo, dou
     double x;
     if (L == 0) return hi;
     x = (S + w / rho) / (double)L;
+    if (x < lo) x = lo;
+    if (x > hi) x = hi;
+    return x;
+}
+
+/* Minimum potential delay fairness (the alpha = 2 member of the alpha-fair
+ * family named in Section II), f(x) = w / x for x > 0: the stationarity
+ * condition -w / x^2 + rho (L x - S) = 0 is the cubic L x^3 - S x^2 - w/rho
+ * = 0, which has one positive root.  Newton's method from
+ * x0 = max(S/L, 0) + (w / (rho L))^(1/3), where the cubic is >= 0 and convex,
+ * decreases monotonically to it. */
+double orc_prox_alpha2(double S, int64_t L, double w, double rho, double lo, double hi)
+{
+    if (L == 0) return hi;
+    const double dl = (double)L, c = w / rho;
+    double x = (S > 0.0 ? S / dl : 0.0) + cbrt(c / dl);
+    for (int it = 0; it < 100; ++it) {
+        const double g = (dl * x - S) * x * x - c;
+        const double dg = (3.0 * dl * x - 2.0 * S) * x;
+        const double nx = x - g / dg;
+        if (!(nx < x)) break;            /* monotone: stop when it stalls */
+        x = nx;
+    }
     if (x < lo) x = lo;
     if (x > hi) x = hi;
     return x;
@@ -232,7 +255,9 @@ int orc_run(const orc_problem *P, const orc_params *prm,
             for (int64_t t = t0; t < t1; ++t) S += z[t] - u[t];
             double xj = P->utility[j] == 0
                 ? orc_prox_log(S, t1 - t0, P->w[j], rho, P->lo, P->hi)
-                : orc_prox_linear(S, t1 - t0, P->w[j], rho, P->lo, P->hi);
+                : P->utility[j] == 1
+                ? orc_prox_linear(S, t1 - t0, P->w[j], rho, P->lo, P->hi)
+                : orc_prox_alpha2(S, t1 - t0, P->w[j], rho, P->lo, P->hi);
             xs[j] = xj;
             for (int64_t t = t0; t < t1; ++t) p[t] = xj;   /* p_sigma = x 1 */
         }

@@ -1,6 +1,6 @@
 // Reverse mode of K unrolled PMP iterations at fixed rho.
 //
-// The objective is J = sum_j U_j(x_j^K) (Section II's utilities at the rates
+// The objective is J = sum_j U_j(x_j^K) (the utilities at the rates
 // of the K-th iteration).  With A, B, Z, U the adjoints of the compact state
 // (a, b, zs, u) and mu_l = [zs_l - u_l > -c_l] the slack-prox mask, one
 // forward iteration t reverses as
@@ -85,7 +85,13 @@ __device__ __forceinline__ void stream_step(const Dev<T> &d, const AdjDev &a, co
     double sbar = 0.0;
     if (L > 0 && x > d.lo && x < d.hi) {
         double dS, dw;
-        if (wsig > 0.0) {
+        if (d.util && d.util[j] == PMP_UTIL_ALPHA2) {
+            // rho L x^3 - rho S x^2 - w = 0:  dx/dS = rho x^3 / (rho L x^3 + 2w),
+            // dx/dw = x / (rho L x^3 + 2w)
+            const double den = rho * (double)L * x * x * x + 2.0 * wsig;
+            dS = rho * x * x * x / den;
+            dw = x / den;
+        } else if (wsig > 0.0) {
             const double den = rho * (double)L * x * x + wsig;
             dS = rho * x * x / den;
             dw = x / den;
@@ -186,7 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_objective(Dev<T> d, double *part)
     double acc = 0.0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
         const double x = (double)d.x[j], ws = (double)d.wsig[j];
-        acc += ws > 0.0 ? ws * log(x) : -ws * x;
+        if (d.util && d.util[j] == PMP_UTIL_ALPHA2) acc += -ws / x;
+        else acc += ws > 0.0 ? ws * log(x) : -ws * x;
     }
     acc = block_sum_d(acc, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -208,8 +215,13 @@ __global__ void k_adj_init(Dev<T> d, AdjDev a)
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
         const double x = (double)d.x[j], ws = (double)d.wsig[j];
         // dJ/dw_j (direct) and dJ/dx_j^K
-        a.wbar[j] = ws > 0.0 ? log(x) : x;
-        a.ext[j] = ws > 0.0 ? ws / x : -ws;
+        if (d.util && d.util[j] == PMP_UTIL_ALPHA2) {
+            a.wbar[j] = -1.0 / x;
+            a.ext[j] = ws / (x * x);
+        } else {
+            a.wbar[j] = ws > 0.0 ? log(x) : x;
+            a.ext[j] = ws > 0.0 ? ws / x : -ws;
+        }
         a.A[j] = 0.0;
         a.Sbar[j] = 0.0;
     }

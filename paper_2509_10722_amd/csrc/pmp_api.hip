@@ -48,8 +48,8 @@ struct Layout {
     bool binned;
     BinnedPlan bp;
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
-    size_t sblk, lblk, spart, lpart, ctl, hist, util, total;
-    int nsb_max, nlb_max;
+    size_t sblk, lblk, spart, lpart, ctl, hist, util, lck_beg, lck_end, lr_row, lr_ck, rpart, total;
+    int nsb_max, nlb_max, nlc_max, nlr_max;
 };
 
 bool use_binned(int m, int n, long long nnz, size_t sz, int layout)
@@ -97,7 +97,14 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
     L.sblk = take(((size_t)L.nsb_max + 1) * 4);
     L.lblk = take(((size_t)L.nlb_max + 1) * 4);
     L.spart = take((size_t)L.nsb_max * 8);
-    L.lpart = take((size_t)L.nlb_max * 16);
+    L.nlr_max = (int)std::min<long long>((long long)m, nnz / (kCap + 1) + 1);
+    L.nlc_max = (int)(nnz / kLongChunk + L.nlr_max + 1);
+    L.lpart = take(((size_t)L.nlb_max + L.nlr_max) * 16);
+    L.lck_beg = take((size_t)L.nlc_max * 4);
+    L.lck_end = take((size_t)L.nlc_max * 4);
+    L.lr_row = take((size_t)L.nlr_max * 4);
+    L.lr_ck = take(((size_t)L.nlr_max + 1) * 4);
+    L.rpart = take((size_t)L.nlc_max * 8);
     L.ctl = take(sizeof(Ctl));
     L.hist = take(sizeof(HistEntry) * kHist);
     L.util = take((size_t)n);
@@ -145,7 +152,7 @@ std::string flag_text(unsigned f)
              "would make R non-0/1); ";
     if (f & kErrCap) s += "capacities must be finite and > 0; ";
     if (f & kErrWeight) s += "weights must be finite and > 0; ";
-    if (f & kErrUtility) s += "utility must be 0 (log) or 1 (linear); ";
+    if (f & kErrUtility) s += "utility must be 0 (log), 1 (linear) or 2 (alpha = 2); ";
     if (f & kErrEmptyRoute) s += "a stream with an empty route needs a finite hi; ";
     return s;
 }
@@ -260,6 +267,11 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     d.lblk = (int *)(ws + L.lblk);
     d.spart = (double *)(ws + L.spart);
     d.lpart = (double *)(ws + L.lpart);
+    d.lck_beg = (int *)(ws + L.lck_beg);
+    d.lck_end = (int *)(ws + L.lck_end);
+    d.lr_row = (int *)(ws + L.lr_row);
+    d.lr_ck = (int *)(ws + L.lr_ck);
+    d.rpart = (double *)(ws + L.rpart);
     d.ctl = (Ctl *)(ws + L.ctl);
     d.hist = (HistEntry *)(ws + L.hist);
     d.lo = p->lo;
@@ -293,7 +305,15 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     Ctl hc;
     HIP_TRY(hipMemcpyAsync(&hc, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (hc.flags) return fail(PMP_ERR_INVALID, "invalid problem: %s", flag_text(hc.flags).c_str());
+    if (hc.flags & ~kHasAlpha2)
+        return fail(PMP_ERR_INVALID, "invalid problem: %s", flag_text(hc.flags).c_str());
+    // utility codes stay on the device only when some stream is alpha = 2
+    d.util = nullptr;
+    if (hc.flags & kHasAlpha2) {
+        if (u_src != (const uint8_t *)(ws + L.util))
+            HIP_TRY(hipMemcpyAsync(ws + L.util, u_src, (size_t)n, hipMemcpyDeviceToDevice, s));
+        d.util = (const uint8_t *)(ws + L.util);
+    }
 
     // CSC pattern (setup step of the stream pass).
     launch_transpose(row_ptr, col_idx, m, n, nnz, col_ptr, row_idx, (int *)(ws + L.a), s);
@@ -307,7 +327,8 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     HIP_TRY(hipMemcpyAsync(hcol.data(), col_ptr, hcol.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&hc, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (hc.flags) return fail(PMP_ERR_INVALID, "invalid problem: %s", flag_text(hc.flags).c_str());
+    if (hc.flags & ~kHasAlpha2)
+        return fail(PMP_ERR_INVALID, "invalid problem: %s", flag_text(hc.flags).c_str());
     std::vector<int> sblk = make_blocks(hcol, n), lblk = make_blocks(hrow, m);
     d.nsb = (int)sblk.size() - 1;
     d.nlb = (int)lblk.size() - 1;
@@ -315,6 +336,31 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         return fail(PMP_ERR_SHAPE, "internal: block tables exceed their bound");
     HIP_TRY(hipMemcpyAsync((void *)d.sblk, sblk.data(), sblk.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((void *)d.lblk, lblk.data(), lblk.size() * 4, hipMemcpyHostToDevice, s));
+    {
+        // rows longer than kCap: chunks of kLongChunk nonzeros
+        std::vector<int> cb, ce, lr, lck{0};
+        for (int l = 0; l < m; ++l) {
+            const int b = hrow[(size_t)l], e = hrow[(size_t)l + 1];
+            if (e - b <= kCap) continue;
+            for (int k = b; k < e; k += kLongChunk) {
+                cb.push_back(k);
+                ce.push_back(std::min(e, k + kLongChunk));
+            }
+            lr.push_back(l);
+            lck.push_back((int)cb.size());
+        }
+        d.nlc = (int)cb.size();
+        d.nlr = (int)lr.size();
+        if (d.nlc > L.nlc_max || d.nlr > L.nlr_max)
+            return fail(PMP_ERR_SHAPE, "internal: long-row tables exceed their bound");
+        if (d.nlc) {
+            HIP_TRY(hipMemcpyAsync((void *)d.lck_beg, cb.data(), cb.size() * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.lck_end, ce.data(), ce.size() * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.lr_row, lr.data(), lr.size() * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.lr_ck, lck.data(), lck.size() * 4, hipMemcpyHostToDevice, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));   // the host vectors go out of scope
+    }
     d.binned = L.binned ? 1 : 0;
     if (L.binned) {
         // tile offsets and local indices of the binned message layout
@@ -368,7 +414,8 @@ void link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t
     if (d.binned) launch_bin_link<T>(d, mode, s);
     else launch_link_pass<T>(d, mode, s);
     if (mode == kCheck)
-        launch_check_finalize<T>(d, d.binned ? d.Q : d.nsb, d.binned ? d.P : d.nlb, delta, stop, s);
+        launch_check_finalize<T>(d, d.binned ? d.Q : d.nsb, d.binned ? d.P : d.nlb + d.nlr, delta,
+                                 stop, s);
 }
 
 // After a check iteration: the u rescale of a balancing step (gather layout:

@@ -409,7 +409,7 @@ pmp_status validate_host(const pmp_problem &p, int i)
     for (int j = 0; j < p.n; ++j) {
         const double w = sz == 8 ? ((const double *)p.w)[j] : ((const float *)p.w)[j];
         if (!(w > 0.0) || !std::isfinite(w)) return set_error(PMP_ERR_INVALID, "batch instance %d: weights must be finite and > 0", i);
-        if (p.utility[j] > 1) return set_error(PMP_ERR_INVALID, "batch instance %d: utility must be 0 or 1", i);
+        if (p.utility[j] > 2) return set_error(PMP_ERR_INVALID, "batch instance %d: utility must be 0, 1 or 2", i);
         if (deg[(size_t)j] == 0 && std::isinf(p.hi))
             return set_error(PMP_ERR_INVALID, "batch instance %d: a stream with an empty route needs a finite hi", i);
     }
@@ -577,6 +577,9 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     BATCH_TRY(hipMemcpyAsync((void *)d.hi, hi.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
     launch_transpose(g.row_ptr, g.col_idx, M, N, E, (int *)g.col_ptr, (int *)g.row_idx, (int *)(ws + L.a), s);
     launch_init_state<T>(g, g.c, g.wsig, (const uint8_t *)(ws + L.util), s);
+    g.util = std::any_of(util.begin(), util.end(), [](uint8_t u) { return u == PMP_UTIL_ALPHA2; })
+                 ? (const uint8_t *)(ws + L.util)
+                 : nullptr;
     launch_fill_int((int *)d.bar, 0, 4, s);
     BATCH_TRY(hipGetLastError());
     std::vector<int> col_ptr((size_t)N + 1);

@@ -86,10 +86,15 @@ namespace {
 // messages are read four at a time (16-byte message and 8-byte index loads,
 // aligned; the arrays carry 4 entries of padding), entries outside
 // [e0, e1) being masked.
+#ifndef PMP_BIN_ACC
+#define PMP_BIN_ACC double
+#endif
+typedef PMP_BIN_ACC acc_t;
+
 template <typename T>
 __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
                                            const uint16_t *__restrict__ idx, int e0, int e1,
-                                           double *acc)
+                                           acc_t *acc)
 {
     if constexpr (sizeof(T) == 4) {
         typedef float f4 __attribute__((ext_vector_type(4)));
@@ -100,14 +105,14 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
             const f4 v = __builtin_nontemporal_load(m4 + b);
             const u4 k = __builtin_nontemporal_load(i4 + b);
             const int e = b << 2;
-            if (e >= e0 && e < e1) unsafeAtomicAdd(&acc[k.x], (double)v.x);
-            if (e + 1 >= e0 && e + 1 < e1) unsafeAtomicAdd(&acc[k.y], (double)v.y);
-            if (e + 2 >= e0 && e + 2 < e1) unsafeAtomicAdd(&acc[k.z], (double)v.z);
-            if (e + 3 >= e0 && e + 3 < e1) unsafeAtomicAdd(&acc[k.w], (double)v.w);
+            if (e >= e0 && e < e1) unsafeAtomicAdd(&acc[k.x], (acc_t)v.x);
+            if (e + 1 >= e0 && e + 1 < e1) unsafeAtomicAdd(&acc[k.y], (acc_t)v.y);
+            if (e + 2 >= e0 && e + 2 < e1) unsafeAtomicAdd(&acc[k.z], (acc_t)v.z);
+            if (e + 3 >= e0 && e + 3 < e1) unsafeAtomicAdd(&acc[k.w], (acc_t)v.w);
         }
     } else {
         for (int e = e0 + threadIdx.x; e < e1; e += kBinThreads)
-            unsafeAtomicAdd(&acc[idx[e]], (double)__builtin_nontemporal_load(msg + e));
+            unsafeAtomicAdd(&acc[idx[e]], (acc_t)__builtin_nontemporal_load(msg + e));
     }
 }
 
@@ -122,7 +127,7 @@ template <typename T>
 __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
                                            const int *__restrict__ dst_off, int dst_stride,
                                            int ntiles, const uint16_t *__restrict__ idx,
-                                           const double *vals, T *__restrict__ out)
+                                           const acc_t *vals, T *__restrict__ out)
 {
     constexpr int W = kBinThreads / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -147,7 +152,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
 {
     if (d.ctl->done) return;
-    extern __shared__ double S[];
+    extern __shared__ acc_t S[];
     __shared__ double sred[kBinThreads / 64];
     const int q = blockIdx.x;
     const int j0 = q * d.SB;
@@ -162,7 +167,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
         const int j = j0 + i;
         const int L = d.col_ptr[j + 1] - d.col_ptr[j];
         const double a = (double)d.a[j];
-        const T xt = (T)prox_stream((double)L * a + S[i], L, (double)d.wsig[j], rho, d.lo, d.hi);
+        const T xt = (T)prox_stream((double)L * a + (double)S[i], L, (double)d.wsig[j], rho, d.lo, d.hi,
+                                    is_alpha2(d, j));
         const double xn = (double)xt;
         if (MODE == kCheck) {                  // dual residual: sum_j L_j (dx_j)^2
             const double dx = xn - (double)d.x[j];
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
         }
         if (MODE != kPlain) d.x[j] = xt;       // otherwise x travels only in the messages
         d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
-        S[i] = xn;
+        S[i] = (acc_t)xn;
     }
     __syncthreads();
     // tile (q, p) of the v messages and tile (p, q) of the x messages list the
@@ -186,7 +192,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kBinThreads) void k_bin_link(Dev<T> d)
 {
     if (d.ctl->done) return;
-    extern __shared__ double Y[];
+    extern __shared__ acc_t Y[];
     __shared__ double sred[kBinThreads / 64];
     const int p = blockIdx.x;
     const int l0 = p * d.LB;
@@ -200,8 +206,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_link(Dev<T> d)
         const int l = l0 + i;
         const int deg = d.row_ptr[l + 1] - d.row_ptr[l];
         // v goes out in the messages; a check stores it for k_bin_emit
-        Y[i] = MODE == kCheck ? link_update<T, MODE, true>(d, l, deg, Y[i], r2, s2)
-                              : link_update<T, MODE, false>(d, l, deg, Y[i], r2, s2);
+        const double y = (double)Y[i];
+        Y[i] = (acc_t)(MODE == kCheck ? link_update<T, MODE, true>(d, l, deg, y, r2, s2)
+                                      : link_update<T, MODE, false>(d, l, deg, y, r2, s2));
     }
     if (MODE != kCheck) {
         __syncthreads();
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_link(Dev<T> d)
 template <typename T>
 __global__ __launch_bounds__(kBinThreads) void k_bin_emit(Dev<T> d, int apply)
 {
-    extern __shared__ double Y[];
+    extern __shared__ acc_t Y[];
     const int p = blockIdx.x;
     const int l0 = p * d.LB;
     const int nl = min(d.LB, d.m - l0);
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_emit(Dev<T> d, int apply)
             vt = (T)((double)d.b[l] - (double)ut);
             d.v[l] = vt;
         }
-        Y[i] = (double)vt;
+        Y[i] = (acc_t)vt;
     }
     __syncthreads();
     emit_tiles<T>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, d.mv);
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_emit(Dev<T> d, int apply)
 
 void binned_configure()
 {
-    const int bytes = kBinMaxBlock * (int)sizeof(double);
+    const int bytes = kBinMaxBlock * (int)sizeof(acc_t);
 #define PMP_BIN_ATTR(K) (void)hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, bytes)
     PMP_BIN_ATTR((k_bin_stream<float, kPlain>));
     PMP_BIN_ATTR((k_bin_stream<float, kSave>));
@@ -269,7 +276,7 @@ void binned_configure()
 template <typename T>
 void launch_bin_stream(const Dev<T> &d, int mode, hipStream_t s)
 {
-    const size_t lds = (size_t)d.SB * sizeof(double);
+    const size_t lds = (size_t)d.SB * sizeof(acc_t);
     switch (mode) {
     case kPlain:
         hipLaunchKernelGGL((k_bin_stream<T, kPlain>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
@@ -286,7 +293,7 @@ void launch_bin_stream(const Dev<T> &d, int mode, hipStream_t s)
 template <typename T>
 void launch_bin_link(const Dev<T> &d, int mode, hipStream_t s)
 {
-    const size_t lds = (size_t)d.LB * sizeof(double);
+    const size_t lds = (size_t)d.LB * sizeof(acc_t);
     switch (mode) {
     case kPlain:
         hipLaunchKernelGGL((k_bin_link<T, kPlain>), dim3(d.P), dim3(kBinThreads), lds, s, d);
@@ -303,7 +310,7 @@ void launch_bin_link(const Dev<T> &d, int mode, hipStream_t s)
 template <typename T>
 void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_bin_emit<T>), dim3(d.P), dim3(kBinThreads), (size_t)d.LB * sizeof(double),
+    hipLaunchKernelGGL((k_bin_emit<T>), dim3(d.P), dim3(kBinThreads), (size_t)d.LB * sizeof(acc_t),
                        s, d, apply);
 }
 

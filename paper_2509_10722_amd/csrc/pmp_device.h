@@ -64,15 +64,28 @@ __device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
 
 // Proximal operator of one traffic stream with L terminals and sum of
 // arguments S (Section III-E), clipped to the box.  wsig > 0: log utility
-// with weight wsig; wsig < 0: linear utility with weight -wsig.  For S < 0 the
-// log root uses the equal form 2w / (rho (sqrt(S^2 + 4wL/rho) - S)).
+// with weight wsig (alpha2 = false) or -w / x with weight wsig (alpha2 =
+// true); wsig < 0: linear utility with weight -wsig.  For S < 0 the log root
+// uses the equal form 2w / (rho (sqrt(S^2 + 4wL/rho) - S)).  The -w / x prox
+// is the positive root of L x^3 - S x^2 - w / rho = 0, reached by Newton's
+// method from max(S/L, 0) + (w / (rho L))^(1/3), where the cubic is
+// nonnegative and convex, so the iterates decrease monotonically.
 __device__ __forceinline__ double prox_stream(double S, int L, double wsig, double rho,
-                                              double lo, double hi)
+                                              double lo, double hi, bool alpha2 = false)
 {
     if (L == 0) return hi;
     double x;
     const double dl = (double)L;
-    if (wsig > 0.0) {
+    if (alpha2) {
+        const double c = wsig / rho;
+        x = (S > 0.0 ? S / dl : 0.0) + cbrt(c / dl);
+        for (int it = 0; it < 100; ++it) {
+            const double g = (dl * x - S) * x * x - c;
+            const double nx = x - g / ((3.0 * dl * x - 2.0 * S) * x);
+            if (!(nx < x)) break;
+            x = nx;
+        }
+    } else if (wsig > 0.0) {
         const double disc = sqrt(S * S + 4.0 * wsig * dl / rho);
         x = S >= 0.0 ? (S + disc) / (2.0 * dl) : 2.0 * wsig / (rho * (disc - S));
     } else {
@@ -81,13 +94,19 @@ __device__ __forceinline__ double prox_stream(double S, int L, double wsig, doub
     return fmin(fmax(x, lo), hi);
 }
 
+template <typename T>
+__device__ __forceinline__ bool is_alpha2(const Dev<T> &d, int j)
+{
+    return d.util != nullptr && d.util[j] == PMP_UTIL_ALPHA2;
+}
+
 template <typename T, bool CHECK>
 __device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, double vsum,
                                                 double rho)
 {
     const double a = (double)d.a[j];
     const double S = (double)L * a + vsum;
-    const T xt = (T)prox_stream(S, L, (double)d.wsig[j], rho, d.lo, d.hi);
+    const T xt = (T)prox_stream(S, L, (double)d.wsig[j], rho, d.lo, d.hi, is_alpha2(d, j));
     const double xn = (double)xt;
     double part = 0.0;
     if (CHECK) {                       // dual residual: sum_j L_j (dx_j)^2

@@ -16,6 +16,10 @@ constexpr int kBlock = 256;
 // A workgroup covers at most kBlock streams (links) and at most kCap
 // nonzeros, or a single longer column (row) on its own.
 constexpr int kCap = 4096;
+// A link whose row holds more than kCap nonzeros (a congested link) is summed
+// by several workgroups, one per chunk of kLongChunk nonzeros; a second
+// kernel adds the chunk sums in chunk order and runs the link update.
+constexpr int kLongChunk = 8192;
 // Device history ring of (iteration, ||r||, ||s||, rho), one entry per check.
 constexpr int kHist = 4096;
 // Threads of the kernel that reduces the residual partials of a check.
@@ -55,6 +59,7 @@ enum : unsigned {
     kErrWeight = 1u << 4,
     kErrUtility = 1u << 5,
     kErrEmptyRoute = 1u << 6,
+    kHasAlpha2 = 1u << 16,   // not an error: some stream has the alpha = 2 utility
 };
 
 // Link-pass flavours: PLAIN does the PMP update only; SAVE also keeps y and
@@ -72,7 +77,8 @@ struct Dev {
     const int *row_ptr, *col_idx;   // CSR
     const int *col_ptr, *row_idx;   // CSC
     const T *c;                     // [m]
-    const T *wsig;                  // [n] w for log streams, -w for linear
+    const T *wsig;                  // [n] w for log / alpha = 2 streams, -w for linear
+    const uint8_t *util;            // [n] utility codes, or NULL when no stream is alpha = 2
     T *a, *x;                       // [n]
     T *b, *zs, *u, *v;              // [m]
     double *y_prev, *ps_prev;       // [m] saved link sums / slack prox
@@ -80,7 +86,11 @@ struct Dev {
     const int *lblk;                // [nlb+1] link workgroup boundaries
     int nsb, nlb;
     double *spart;                  // [nsb]   stream residual partials
-    double *lpart;                  // [2 nlb] link residual partials
+    double *lpart;                  // [2 (nlb + nlr)] link residual partials
+    int nlc, nlr;                   // chunks of long rows, long rows
+    const int *lck_beg, *lck_end;   // [nlc] nonzero range of each chunk
+    const int *lr_row, *lr_ck;      // [nlr], [nlr + 1] long rows and their chunks
+    double *rpart;                  // [nlc] chunk sums
     double lo, hi, alpha;
     Ctl *ctl;
     HistEntry *hist;
@@ -135,8 +145,14 @@ template <typename T>
 void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s);
 
 // Binned layout (pmp_binned.hip).
-constexpr int kBinThreads = 1024;          // threads per binned workgroup
-constexpr int kBinMaxBlock = 10240;        // links / streams per binned workgroup
+#ifndef PMP_BIN_THREADS
+#define PMP_BIN_THREADS 1024
+#endif
+#ifndef PMP_BIN_MAX_BLOCK
+#define PMP_BIN_MAX_BLOCK 10240
+#endif
+constexpr int kBinThreads = PMP_BIN_THREADS;       // threads per binned workgroup
+constexpr int kBinMaxBlock = PMP_BIN_MAX_BLOCK;    // links / streams per binned workgroup
 struct BinnedPlan {
     int P, Q, LB, SB;
 };

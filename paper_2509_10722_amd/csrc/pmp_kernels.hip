@@ -66,6 +66,16 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d)
     __shared__ T sx[kCap];
     __shared__ double sred[kBlock / 64];
     const int blk = blockIdx.x;
+    if (blk >= d.nlb) {
+        // one chunk of a long row: a partial sum in a fixed order
+        const int c = blk - d.nlb;
+        double acc = 0.0;
+        for (int k = d.lck_beg[c] + threadIdx.x; k < d.lck_end[c]; k += kBlock)
+            acc += (double)d.x[ld_stream(d.col_idx + k)];
+        acc = block_sum(acc, sred);
+        if (threadIdx.x == 0) d.rpart[c] = acc;
+        return;
+    }
     const int l0 = d.lblk[blk], l1 = d.lblk[blk + 1];
     const int e0 = d.row_ptr[l0];
     const int cnt = d.row_ptr[l1] - e0;
@@ -80,19 +90,32 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d)
             for (int k = b; k < e; ++k) acc += (double)sx[k];
             link_update<T, MODE>(d, l, e - b, acc, r2, s2);
         }
-    } else {
-        double acc = 0.0;
-        for (int k = threadIdx.x; k < cnt; k += kBlock)
-            acc += (double)d.x[ld_stream(d.col_idx + e0 + k)];
-        acc = block_sum(acc, sred);
-        if (threadIdx.x == 0) link_update<T, MODE>(d, l0, cnt, acc, r2, s2);
     }
+    // a longer row is one of the long rows: its chunks and k_long_rows do it
     if (MODE == kCheck) {
         r2 = block_sum(r2, sred);
         s2 = block_sum(s2, sred);
         if (threadIdx.x == 0) {
             d.lpart[2 * blk] = r2;
             d.lpart[2 * blk + 1] = s2;
+        }
+    }
+}
+
+// Long rows: add each row's chunk sums in chunk order, then the link update.
+template <typename T, int MODE>
+__global__ void k_long_rows(Dev<T> d)
+{
+    if (d.ctl->done) return;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.nlr; r += gridDim.x * blockDim.x) {
+        const int l = d.lr_row[r];
+        double y = 0.0;
+        for (int c = d.lr_ck[r]; c < d.lr_ck[r + 1]; ++c) y += d.rpart[c];
+        double r2 = 0.0, s2 = 0.0;
+        link_update<T, MODE>(d, l, d.row_ptr[l + 1] - d.row_ptr[l], y, r2, s2);
+        if (MODE == kCheck) {
+            d.lpart[2 * (d.nlb + r)] = r2;
+            d.lpart[2 * (d.nlb + r) + 1] = s2;
         }
     }
 }
@@ -144,7 +167,7 @@ __global__ void k_init_state(Dev<T> d, const T *c_in, const T *w_in, const uint8
     const int stride = gridDim.x * blockDim.x;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
         const T w = w_in[j];
-        const_cast<T *>(d.wsig)[j] = util[j] ? -w : w;
+        const_cast<T *>(d.wsig)[j] = util[j] == PMP_UTIL_LINEAR ? -w : w;
         d.a[j] = T(0);
         d.x[j] = T(0);
     }
@@ -190,7 +213,8 @@ __global__ void k_check_vectors(const T *c, const T *w, const uint8_t *util, int
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         const double v = (double)w[j];
         if (!(v > 0.0) || !isfinite(v)) f |= kErrWeight;
-        if (util[j] > 1) f |= kErrUtility;
+        if (util[j] > 2) f |= kErrUtility;
+        if (util[j] == 2) f |= kHasAlpha2;
     }
     if (f) atomicOr(&ctl->flags, f);
 }
@@ -426,15 +450,20 @@ template <typename T>
 void launch_link_pass(const Dev<T> &d, int mode, hipStream_t s)
 {
     if (d.nlb == 0) return;
+    const int grid = d.nlb + d.nlc;
+    const int lg = d.nlr > 0 ? (d.nlr + 63) / 64 : 0;
     switch (mode) {
     case kPlain:
-        hipLaunchKernelGGL((k_link_pass<T, kPlain>), dim3(d.nlb), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL((k_link_pass<T, kPlain>), dim3(grid), dim3(kBlock), 0, s, d);
+        if (lg) hipLaunchKernelGGL((k_long_rows<T, kPlain>), dim3(lg), dim3(64), 0, s, d);
         break;
     case kSave:
-        hipLaunchKernelGGL((k_link_pass<T, kSave>), dim3(d.nlb), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL((k_link_pass<T, kSave>), dim3(grid), dim3(kBlock), 0, s, d);
+        if (lg) hipLaunchKernelGGL((k_long_rows<T, kSave>), dim3(lg), dim3(64), 0, s, d);
         break;
     default:
-        hipLaunchKernelGGL((k_link_pass<T, kCheck>), dim3(d.nlb), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL((k_link_pass<T, kCheck>), dim3(grid), dim3(kBlock), 0, s, d);
+        if (lg) hipLaunchKernelGGL((k_long_rows<T, kCheck>), dim3(lg), dim3(64), 0, s, d);
         break;
     }
 }

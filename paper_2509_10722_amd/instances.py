@@ -32,6 +32,7 @@ import numpy as np
 
 LOG = 0
 LINEAR = 1
+ALPHA2 = 2      # -w / x, minimum potential delay fairness
 
 
 @dataclasses.dataclass
@@ -247,6 +248,26 @@ def block_diagonal(parts):
                     np.concatenate([p.c for p in parts]),
                     np.concatenate([p.w for p in parts]),
                     np.concatenate([p.utility for p in parts]).astype(np.uint8), lo, hi)
+
+
+def congested(base, link_frac=0.001, stream_frac=0.10, seed=6):
+    """Section V-C's congestion: a random `link_frac` of the links is each
+    added to the routes of a random `stream_frac` of the streams (pairs that
+    already exist are kept once).  Capacities and weights are kept."""
+    rng = np.random.default_rng(seed)
+    m, n = base.m, base.n
+    k = max(1, int(round(link_frac * m)))
+    hot = rng.choice(m, k, replace=False)
+    per = max(1, int(round(stream_frac * n)))
+    rows = np.repeat(np.arange(m, dtype=np.int64), np.diff(base.row_ptr))
+    links = [rows, np.repeat(hot.astype(np.int64), per)]
+    streams = [base.col_idx.astype(np.int64)]
+    for _ in hot:
+        streams.append(rng.choice(n, per, replace=False).astype(np.int64))
+    key = np.unique(np.concatenate(links) * n + np.concatenate(streams))
+    row_ptr, col_idx = csr_from_pairs(m, n, key // n, key % n)
+    return Instance(base.name + "_congested", m, n, row_ptr, col_idx, base.c, base.w,
+                    base.utility, base.lo, base.hi)
 
 
 CONFIGS = {"tiny": tiny, "medium": medium, "large": large, "adjoint": adjoint,

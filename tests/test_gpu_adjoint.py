@@ -144,3 +144,28 @@ def test_autograd_function_fp32():
     solver.close(); ref.close()
     assert rel(host(c.grad), host(gc64)) <= 1e-4
     assert rel(host(w.grad), host(gw64)) <= 1e-4
+
+
+def test_adjoint_alpha2_directional_fd():
+    inst = I.tiny(seed=9)
+    rng = np.random.default_rng(9)
+    inst.utility = rng.integers(0, 3, inst.n).astype(np.uint8)
+    K = 120
+    solver = Solver(inst, dtype=torch.float64, adapt_every=0)
+    solver.forward_ckpt(K, 16)
+    gc, gw = solver.backward()
+    solver.close()
+    dc = rng.normal(size=inst.m)
+    dw = rng.normal(size=inst.n)
+    h = 1e-6
+
+    def J_at(t):
+        p = I.Instance(inst.name, inst.m, inst.n, inst.row_ptr, inst.col_idx,
+                       inst.c + t * dc, inst.w + t * dw, inst.utility, inst.lo, inst.hi)
+        x = oracle.run(p, K, adapt_every=0)["x"]
+        return opt.utility(p, x)
+
+    fd = (J_at(h) - J_at(-h)) / (2 * h)
+    an = float(host(gc) @ dc + host(gw) @ dw)
+    print(f"alpha2 directional derivative: adjoint {an:.10g}, FD {fd:.10g}")
+    assert abs(an - fd) <= 1e-5 * max(1.0, abs(fd))

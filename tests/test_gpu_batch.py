@@ -108,3 +108,18 @@ def test_stream_reordering_keeps_results():
         b.close()
     for (x0, l0, s0), (x1, l1, s1) in zip(*outs):
         assert np.array_equal(x0, x1) and np.array_equal(l0, l1) and np.array_equal(s0, s1)
+
+
+def test_batch_with_alpha2_instance():
+    a = I.tiny(seed=4)
+    a.utility = np.random.default_rng(4).integers(0, 3, a.n).astype(np.uint8)
+    insts = [a] + _small_batch(count=2)
+    for i in insts:
+        i.lo, i.hi = 0.0, float(max(i.hi, 10.0))
+    b = BatchSolver(insts, dtype=torch.float64, eps_abs=0.0)
+    b.solve(150)
+    for k, inst in enumerate(insts):
+        o = oracle.run(inst, 150)
+        xb, lb, _ = b.solution(k)
+        assert rel(host(xb), o["x"]) <= 1e-10 and rel(host(lb), o["lam"]) <= 1e-10
+    b.close()

@@ -275,3 +275,34 @@ def test_host_and_device_inputs_agree():
     a = _run_gpu(inst, 200, torch.float32, memory="host")
     b = _run_gpu(inst, 200, torch.float32, memory="device")
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["lam"], b["lam"])
+
+
+def _alpha2_instance(seed=21):
+    inst = I.tiny(seed=seed)
+    rng = np.random.default_rng(seed)
+    inst.utility = rng.integers(0, 3, inst.n).astype(np.uint8)
+    return inst
+
+
+@pytest.mark.parametrize("dtype_name,tol", [("float64", 1e-10), ("float32", 1e-5)])
+def test_alpha2_utility_equal_iterations(dtype_name, tol):
+    inst = _alpha2_instance()
+    if dtype_name == "float32":
+        inst = inst.rounded(np.float32)
+    K = 800
+    g = _run_gpu(inst, K, getattr(torch, dtype_name))
+    o = oracle.run(inst, K)
+    print(f"alpha2 mix {dtype_name}: x {rel(g['x'], o['x']):.2e} lam {rel(g['lam'], o['lam']):.2e}")
+    assert rel(g["x"], o["x"]) <= tol and rel(g["lam"], o["lam"]) <= tol
+
+
+def test_alpha2_single_link_closed_form():
+    w = np.array([0.5, 1.0, 1.7, 2.0])
+    inst = I.single_link(w, [2] * 4, 6.0, hi=1e3)
+    s = Solver(inst, dtype=torch.float64, eps_abs=1e-12, max_iter=100000)
+    assert s.solve()["converged"]
+    x, lam, _ = s.solution()
+    s.close()
+    xs, ls = opt.single_link_alpha2(w, 6.0)
+    np.testing.assert_allclose(host(x), xs, rtol=1e-8)
+    np.testing.assert_allclose(host(lam), [ls], rtol=1e-7)

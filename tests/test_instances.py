@@ -63,3 +63,18 @@ def test_block_diagonal():
     u = I.block_diagonal([a, b])
     _check_pattern(u)
     assert u.m == 4 and u.n == 6 and u.nnz == 7
+
+
+def test_congested_adds_dense_rows():
+    base = I.medium(scale=0.05)
+    c = I.congested(base, link_frac=0.002, stream_frac=0.1)
+    _check_pattern(c)
+    deg = np.diff(c.row_ptr)
+    hot = np.argsort(deg)[-10:]
+    assert deg[hot].min() >= 0.1 * base.n * 0.99
+    assert c.nnz > base.nnz
+    # every original pair is still there
+    rows = np.repeat(np.arange(base.m), np.diff(base.row_ptr))
+    rows_c = np.repeat(np.arange(c.m), np.diff(c.row_ptr))
+    orig = set((rows * base.n + base.col_idx).tolist())
+    assert orig <= set((rows_c * c.n + c.col_idx).tolist())

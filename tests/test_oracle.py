@@ -312,3 +312,42 @@ def test_matches_printed_overrelaxed_updates(alpha):
         r = oracle.run(inst, 60, alpha=alpha, rho0=1.3, adapt_every=0)
         np.testing.assert_allclose(r["x"], xp, rtol=1e-11, atol=1e-12)
         np.testing.assert_allclose(r["lam"], lp, rtol=1e-10, atol=1e-12)
+
+
+# ---- alpha = 2 fairness (named in Section II) -------------------------------
+
+@pytest.mark.parametrize("seed", range(30))
+def test_prox_alpha2_matches_minimisation(seed):
+    rng = np.random.default_rng(500 + seed)
+    L = int(rng.integers(1, 12))
+    zetas = rng.normal(0, 3, L) * rng.choice([0.01, 1, 30])
+    w = rng.uniform(0.1, 3)
+    rho = rng.choice([0.1, 1.0, 7.0])
+    hi = float(rng.choice([5.0, 50.0, 1e3]))
+    x = oracle.prox_alpha2(float(zetas.sum()), L, w, rho, 0.0, hi)
+    xr = _numeric_prox(lambda v: w / v, zetas, rho, 1e-9, hi)
+    assert abs(x - xr) <= 1e-6 * max(1.0, abs(xr))
+
+
+def test_single_link_alpha2_closed_form():
+    w = np.array([0.5, 1.0, 1.7, 2.0])
+    inst = I.single_link(w, [2] * 4, 6.0)
+    r = oracle.run(inst, 50000, eps_abs=1e-12, stop=True)
+    assert r["converged"]
+    x, lam = opt.single_link_alpha2(w, 6.0)
+    np.testing.assert_allclose(r["x"], x, rtol=1e-8)
+    np.testing.assert_allclose(r["lam"], [lam], rtol=1e-7)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_alpha2_mixed_brute_force_and_kkt(seed):
+    inst = _tiny_random(30 + seed)
+    rng = np.random.default_rng(seed)
+    inst.utility = rng.integers(0, 3, inst.n).astype(np.uint8)
+    r = oracle.run(inst, 300000, eps_abs=1e-10, stop=True)
+    assert r["converged"]
+    bf = opt.brute_force(inst)
+    U = opt.utility(inst, r["x"])
+    assert abs(U - bf["primal_obj"]) < 1e-6 * max(1.0, abs(U))
+    rep = opt.kkt_report(inst, r["x"], r["lam"])
+    assert rep["rel_gap"] < 1e-7 and rep["stationarity_log"] < 1e-5
