@@ -118,9 +118,11 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
 
 // Write the messages of one workgroup's tiles.  Wave w takes tiles
 // w, w + W, w + 2W, ... (W waves).  Lane i first loads the offsets of the
-// wave's i-th tile of the next 64, so those loads overlap; the wave then walks
-// the tiles, taking each tile's offsets from the owning lane and writing the
-// tile with all 64 lanes.
+// wave's i-th tile of the next 64.  The wave then writes its tiles four at a
+// time: every lane loads the local indices of its entries in all four tiles
+// (up to two entries per tile) before any value is looked up and stored, so
+// eight index loads per lane are in flight; entries of longer tiles follow in
+// a tail loop.
 //   src_off[t], src_off[t + 1]   tile t in the read layout (index array idx)
 //   dst_off[t * dst_stride]      tile t in the written layout
 template <typename T>
@@ -130,6 +132,7 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
                                            const acc_t *vals, T *__restrict__ out)
 {
     constexpr int W = kBinThreads / 64;
+    constexpr int U = 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int mine = ntiles > wave ? (ntiles - wave + W - 1) / W : 0;   // tiles of this wave
     for (int base = 0; base < mine; base += 64) {
@@ -141,9 +144,32 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
             dst = dst_off[(long long)t * dst_stride];
         }
         const int nt = min(64, mine - base);
-        for (int i = 0; i < nt; ++i) {
-            const int s_i = __shfl(src, i, 64), c_i = __shfl(cnt, i, 64), d_i = __shfl(dst, i, 64);
-            for (int k = lane; k < c_i; k += 64) out[d_i + k] = (T)vals[idx[s_i + k]];
+        for (int i0 = 0; i0 < nt; i0 += U) {
+            int s_u[U], c_u[U], d_u[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = min(i0 + u, nt - 1);
+                s_u[u] = __shfl(src, i, 64);
+                c_u[u] = i0 + u < nt ? __shfl(cnt, i, 64) : 0;
+                d_u[u] = __shfl(dst, i, 64);
+            }
+            int id[U][2];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int k = lane + 64 * r;
+                    id[u][r] = k < c_u[u] ? (int)idx[s_u[u] + k] : -1;
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                    if (id[u][r] >= 0) out[d_u[u] + lane + 64 * r] = (T)vals[id[u][r]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                for (int k = lane + 128; k < c_u[u]; k += 64)
+                    out[d_u[u] + k] = (T)vals[idx[s_u[u] + k]];
         }
     }
 }
