@@ -79,7 +79,7 @@ def bench_batched(args, log):
         opts, timings = autotune.tune_batch(insts, dtype=torch.float32, log=log)
     else:
         opts = autotune.cached_options(torch)
-    caps = list(opts.tile_cap)
+    caps = list(opts.tile_cap) + [int(opts.wg_per_cu)]
     b = BatchSolver(insts, dtype=torch.float32, options=opts)
     b.solve(20)                     # warm-up: graph capture, first touch
     b.reset()
@@ -112,7 +112,8 @@ def bench_batched(args, log):
         "metric": "batched PMP instance-iterations/sec (64 transit instances, to 1e-4)",
         "value": round(sum(iters) / tb, 1), "unit": "instance-iter/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched transit x{len(insts)}", **tot, "tile_cap": caps},
+        "config": {"workload": f"batched transit x{len(insts)}", **tot,
+                   "tile_cap": caps[:3], "wg_per_cu": caps[3]},
         "time_s": round(tb, 4), "plain_time_s": round(tp, 4),
         "speedup_vs_plain": round(tp / tb, 3), "converged": conv,
         "iterations_equal_plain": sum(int(a == c) for a, c in zip(iters, plain_iters)),

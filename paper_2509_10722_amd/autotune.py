@@ -7,8 +7,10 @@ across workgroups when instances are small and stop at different times);
 large caps give fewer, longer tiles (more gathers in flight per workgroup).
 The tuner times a fixed number of batch iterations for each candidate cap,
 one size class at a time (the other classes held at their current best), and
-keeps the fastest.  Results are cached per GPU architecture and size class
-in a JSON file.
+keeps the fastest; it then picks the number of resident workgroups per CU
+of the persistent grid (more hide latency, fewer make the grid barriers
+cheaper).  Results are cached per GPU architecture and size class in a JSON
+file.
 """
 from __future__ import annotations
 
@@ -17,6 +19,7 @@ import os
 import time
 
 CANDIDATES = (512, 1024, 2048, 4096)
+GRID_CANDIDATES = (1, 2, 4, 8)          # resident workgroups per CU
 CLASS_NAMES = ("small", "medium", "large")
 
 
@@ -49,6 +52,8 @@ def cached_options(torch, path=None):
         key = f"{arch}:{name}"
         if key in cache:
             o.tile_cap[c] = int(cache[key]["tile_cap"])
+    if f"{arch}:grid" in cache:
+        o.wg_per_cu = int(cache[f"{arch}:grid"]["wg_per_cu"])
     return o
 
 
@@ -94,11 +99,22 @@ def tune_batch(insts, dtype=None, iters=60, reps=2, candidates=CANDIDATES, path=
             if best_t is None or t < best_t:
                 best_cap, best_t = cap, t
         opts.tile_cap[c] = best_cap
+    best_g, best_t = opts.wg_per_cu, None
+    for g in GRID_CANDIDATES:
+        opts.wg_per_cu = g
+        t = _time_batch(insts, dtype, opts, iters, reps, **kw)
+        timings[f"grid:{g}"] = t
+        if log:
+            log(f"[tune] {g} workgroups per CU: {t * 1e3:.2f} ms / {iters} it")
+        if best_t is None or t < best_t:
+            best_g, best_t = g, t
+    opts.wg_per_cu = best_g
     path = path or default_cache_path()
     cache = load_cache(path)
     arch = _arch(torch)
     for c in sorted(present):
         cache[f"{arch}:{CLASS_NAMES[c]}"] = {"tile_cap": int(opts.tile_cap[c])}
+    cache[f"{arch}:grid"] = {"wg_per_cu": int(opts.wg_per_cu)}
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -249,7 +249,7 @@ void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int
 }
 
 template <typename T>
-int batch_grid_size(int device)
+int batch_grid_size(int device, int want_per_cu)
 {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch<T>, kBlock, 0) !=
@@ -257,17 +257,17 @@ int batch_grid_size(int device)
         return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
-    // at most 4 resident workgroups per CU take part: enough to cover latency,
-    // few enough to keep the barriers short
-    return std::min(per_cu, 4) * cus;
+    // a few resident workgroups per CU: enough to cover latency, few enough to
+    // keep the grid barriers short (tunable)
+    return std::min(per_cu, want_per_cu > 0 ? want_per_cu : 4) * cus;
 }
 
 template void launch_batch_gather_x<float>(const float *, const int *, int, float *, hipStream_t);
 template void launch_batch_gather_x<double>(const double *, const int *, int, double *, hipStream_t);
 template void launch_batch<float>(const BDev<float> &, int, int, int, int, hipStream_t);
 template void launch_batch<double>(const BDev<double> &, int, int, int, int, hipStream_t);
-template int batch_grid_size<float>(int);
-template int batch_grid_size<double>(int);
+template int batch_grid_size<float>(int, int);
+template int batch_grid_size<double>(int, int);
 
 
 // ---- host side ----------------------------------------------------------------
@@ -608,7 +608,7 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     if (st != PMP_OK) return st;
     int dev = 0;
     BATCH_TRY(hipGetDevice(&dev));
-    b->grid = batch_grid_size<T>(dev);
+    b->grid = batch_grid_size<T>(dev, opt->wg_per_cu);
     if (b->grid < 1) return set_error(PMP_ERR_HIP, "occupancy query for the batch kernel failed");
     BATCH_TRY(hipStreamSynchronize(s));
     return PMP_OK;
@@ -691,6 +691,7 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     o->tile_cap[1] = 2048;
     o->tile_cap[2] = 4096;
     o->reorder_streams = 1;
+    o->wg_per_cu = 4;
     return PMP_OK;
 }
 
@@ -701,6 +702,8 @@ static pmp_status check_batch_args(int32_t count, const pmp_problem *pr, const p
     for (int c = 0; c < 3; ++c)
         if (opt->tile_cap[c] < 64 || opt->tile_cap[c] > kCap)
             return set_error(PMP_ERR_INVALID, "tile_cap must be in [64, %d]", kCap);
+    if (opt->wg_per_cu < 0 || opt->wg_per_cu > 8)
+        return set_error(PMP_ERR_INVALID, "wg_per_cu must be in [0, 8]");
     for (int i = 1; i < count; ++i)
         if (pr[i].dtype != pr[0].dtype) return set_error(PMP_ERR_INVALID, "batch instances must share the dtype");
     if (!sizes_of(count, pr, z)) return set_error(PMP_ERR_SHAPE, "batch sizes out of range (m >= 1; totals < 2^31)");

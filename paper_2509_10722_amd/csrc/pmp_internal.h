@@ -199,7 +199,7 @@ template <typename T>
 void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int adapt_every,
                   hipStream_t s);
 template <typename T>
-int batch_grid_size(int device);
+int batch_grid_size(int device, int want_per_cu);
 template <typename T>
 void launch_batch_gather_x(const T *x, const int *pos, int n, T *out, hipStream_t s);
 

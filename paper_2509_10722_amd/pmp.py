@@ -354,7 +354,7 @@ def pmp_objective(c, w, solver, K, s=25):
 
 class pmp_batch_options(ctypes.Structure):
     _fields_ = [("class_m", ctypes.c_int32 * 2), ("tile_cap", ctypes.c_int32 * 3),
-                ("reorder_streams", ctypes.c_int32)]
+                ("reorder_streams", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
 
 
 _BATCH_SIGNATURES = {
@@ -384,6 +384,8 @@ def batch_options_default(**caps) -> pmp_batch_options:
             o.class_m[i] = int(v)
     if "reorder_streams" in caps:
         o.reorder_streams = int(caps["reorder_streams"])
+    if "wg_per_cu" in caps:
+        o.wg_per_cu = int(caps["wg_per_cu"])
     return o
 
 
