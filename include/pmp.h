@@ -180,6 +180,39 @@ pmp_status pmp_set_state(pmp_handle *h, const void *state);
  * iterate: the warm-started re-solve after degradation of Section V-D. */
 pmp_status pmp_update_capacity(pmp_handle *h, const void *c_new);
 
+/* Link failure and pruning (Section V-D).  failed[m] (device, uint8,
+ * nonzero = the link failed) removes those links and every stream whose
+ * route uses one of them; the survivors are renumbered in their old order
+ * and each surviving row keeps its surviving entries in column order.
+ * Outputs are device memory sized for the current (unpruned) instance; the
+ * first m', n', nnz' entries are written:
+ *   row_ptr[m+1], col_idx[nnz]    CSR of the pruned R (int32)
+ *   c[m]                          current capacities of the surviving links
+ *   w[n], utility[n]              weights (> 0) and codes of the survivors
+ *   link_map[m], stream_map[n]    old index of each surviving link / stream
+ *   state[pmp_state_size bytes]   the current iterate restricted to the
+ *                                 survivors, in the pmp_set_state layout of
+ *                                 the pruned instance (rho carried over,
+ *                                 iteration count 0): the warm start
+ * c, w and state use the problem dtype.  sizes (host) receives m', n', nnz'.
+ * `workspace` is device scratch of pmp_prune_workspace_size bytes.  The
+ * handle itself is unchanged; the pruned instance is set up with pmp_setup
+ * (same lo, hi) and warm-started with pmp_set_state.  m' or n' may be 0
+ * (pmp_setup rejects m' = 0).  Synchronises the handle's stream.
+ * PMP_ERR_INVALID for a NULL pointer or a short workspace. */
+pmp_status pmp_prune_workspace_size(pmp_handle *h, size_t *bytes);
+pmp_status pmp_prune(pmp_handle *h, const uint8_t *failed, void *workspace,
+                     size_t workspace_bytes, int32_t *row_ptr, int32_t *col_idx, void *c,
+                     void *w, uint8_t *utility, int32_t *link_map, int32_t *stream_map,
+                     void *state, int64_t *sizes);
+
+/* Path prices (Section VI-B): pi[n] = sum over the links l of route j of
+ * lambda_l = rho u_l, the price stream j pays per unit rate; at the optimum
+ * pi_j = U_j'(x_j) for an interior x_j.  pi is device memory of the
+ * problem's dtype; the sum is formed in FP64.  Synchronises the handle's
+ * stream. */
+pmp_status pmp_get_path_prices(pmp_handle *h, void *pi);
+
 /* Device pointers to the internal rate and price-related vectors (x[n] and
  * u[m]) for zero-copy inspection; valid until pmp_destroy. */
 pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **b,

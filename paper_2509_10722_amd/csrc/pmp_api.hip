@@ -914,6 +914,52 @@ pmp_status pmp_get_solution(pmp_handle *h, void *x, void *lambda, void *slack)
     return PMP_OK;
 }
 
+pmp_status pmp_get_path_prices(pmp_handle *h, void *pi)
+{
+    if (!h || !pi) return fail(PMP_ERR_INVALID, "NULL argument");
+    if (h->dtype == PMP_F32)
+        launch_path_prices<float>(h->df, (float *)pi, h->stream);
+    else
+        launch_path_prices<double>(h->dd, (double *)pi, h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return PMP_OK;
+}
+
+pmp_status pmp_prune_workspace_size(pmp_handle *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(PMP_ERR_INVALID, "NULL argument");
+    *bytes = prune_scratch_ints(h->m, h->n) * 4;
+    return PMP_OK;
+}
+
+pmp_status pmp_prune(pmp_handle *h, const uint8_t *failed, void *workspace,
+                     size_t workspace_bytes, int32_t *row_ptr, int32_t *col_idx, void *c,
+                     void *w, uint8_t *utility, int32_t *link_map, int32_t *stream_map,
+                     void *state, int64_t *sizes)
+{
+    if (!h || !failed || !workspace || !row_ptr || !c || !link_map || !state || !sizes)
+        return fail(PMP_ERR_INVALID, "NULL argument");
+    if ((h->nnz > 0 && !col_idx) || (h->n > 0 && (!w || !utility || !stream_map)))
+        return fail(PMP_ERR_INVALID, "NULL argument");
+    if (workspace_bytes < prune_scratch_ints(h->m, h->n) * 4)
+        return fail(PMP_ERR_INVALID, "workspace of %zu bytes is below the %zu required",
+                    workspace_bytes, prune_scratch_ints(h->m, h->n) * 4);
+    long long sz[3] = {0, 0, 0};
+    hipError_t e;
+    if (h->dtype == PMP_F32)
+        e = prune_device<float>(h->df, failed, (int *)workspace, row_ptr, col_idx, (float *)c,
+                                (float *)w, utility, link_map, stream_map, (char *)state, sz,
+                                h->stream);
+    else
+        e = prune_device<double>(h->dd, failed, (int *)workspace, row_ptr, col_idx, (double *)c,
+                                 (double *)w, utility, link_map, stream_map, (char *)state, sz,
+                                 h->stream);
+    if (e != hipSuccess) return fail(PMP_ERR_HIP, "pruning failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < 3; ++i) sizes[i] = sz[i];
+    return PMP_OK;
+}
+
 pmp_status pmp_state_size(pmp_handle *h, size_t *bytes)
 {
     if (!h || !bytes) return fail(PMP_ERR_INVALID, "NULL argument");

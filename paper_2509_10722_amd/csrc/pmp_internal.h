@@ -143,6 +143,16 @@ template <typename T>
 void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s);
 template <typename T>
 void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s);
+template <typename T>
+void launch_path_prices(const Dev<T> &d, T *pi, hipStream_t s);
+
+// Link failure compaction (pmp_prune.hip).  scratch holds
+// prune_scratch_ints(m, n) ints; sizes receives m', n', nnz'.  Synchronises s.
+size_t prune_scratch_ints(int m, int n);
+template <typename T>
+hipError_t prune_device(const Dev<T> &d, const uint8_t *failed, int *scratch, int *row_ptr,
+                        int *col_idx, T *c, T *w, uint8_t *util, int *link_map, int *stream_map,
+                        char *state, long long sizes[3], hipStream_t s);
 
 // Binned layout (pmp_binned.hip).
 #ifndef PMP_BIN_THREADS

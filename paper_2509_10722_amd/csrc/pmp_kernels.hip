@@ -413,6 +413,19 @@ __global__ void k_solution(Dev<T> d, T *x, T *lambda, T *slack)
     }
 }
 
+// pi_j = rho sum_{l in route j} u_l (CSC walk, FP64 sum in route order).
+template <typename T>
+__global__ void k_path_prices(Dev<T> d, T *pi)
+{
+    const double rho = d.ctl->rho;
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
+        double s = 0.0;
+        for (int k = d.col_ptr[j]; k < d.col_ptr[j + 1]; ++k) s += (double)d.u[d.row_idx[k]];
+        pi[j] = (T)(rho * s);
+    }
+}
+
 template <typename T>
 __global__ void k_copy_capacity(Dev<T> d, const T *c_new)
 {
@@ -525,6 +538,14 @@ void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s)
                        s, d, c_new);
 }
 
+template <typename T>
+void launch_path_prices(const Dev<T> &d, T *pi, hipStream_t s)
+{
+    if (d.n == 0) return;
+    hipLaunchKernelGGL((k_path_prices<T>), dim3(grid_for(d.n, kBlock, 16384)), dim3(kBlock), 0, s,
+                       d, pi);
+}
+
 void launch_validate_csr(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
                          Ctl *ctl, hipStream_t s)
 {
@@ -538,23 +559,33 @@ size_t transpose_scratch_ints(int n)
     return (size_t)n + nb + 1;
 }
 
+size_t scan_scratch_ints(int n)
+{
+    return ((size_t)n + kScanTile - 1) / kScanTile + 1;
+}
+
+void launch_scan_int(const int *in, int n, int *out, int *bsum, hipStream_t s)
+{
+    if (n > 0) {
+        const int nb = (int)(((long long)n + kScanTile - 1) / kScanTile);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, n, bsum);
+        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsum, nb);
+        hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, in, n, bsum, out);
+    } else {
+        launch_fill_int(out, 0, 1, s);
+    }
+}
+
 void launch_transpose(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
                       int *col_ptr, int *row_idx, int *tmp, hipStream_t s)
 {
     int *count = tmp;
-    const int nb = (int)(((long long)n + kScanTile - 1) / kScanTile);
     int *bsum = tmp + n;
     launch_fill_int(count, 0, (size_t)n, s);
     if (nnz > 0)
         hipLaunchKernelGGL(k_histogram, dim3(grid_for(nnz, kBlock, 65536)), dim3(kBlock), 0, s,
                            col_idx, nnz, count);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, count, n, bsum);
-        hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsum, nb);
-        hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, count, n, bsum, col_ptr);
-    } else {
-        launch_fill_int(col_ptr, 0, 1, s);
-    }
+    launch_scan_int(count, n, col_ptr, bsum, s);
     launch_fill_int(count, 0, (size_t)n, s);
     if (m > 0)
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, kBlock, 65536)), dim3(kBlock), 0, s,
@@ -608,7 +639,8 @@ void launch_fill_int(int *p, int value, size_t count, hipStream_t s)
     template void launch_check_vectors<T>(const T *, const T *, const uint8_t *, int, int, \
                                           Ctl *, hipStream_t);                              \
     template void launch_solution<T>(const Dev<T> &, T *, T *, T *, hipStream_t);           \
-    template void launch_copy_capacity<T>(const Dev<T> &, const T *, hipStream_t);
+    template void launch_copy_capacity<T>(const Dev<T> &, const T *, hipStream_t);         \
+    template void launch_path_prices<T>(const Dev<T> &, T *, hipStream_t);
 
 PMP_INSTANTIATE(float)
 PMP_INSTANTIATE(double)

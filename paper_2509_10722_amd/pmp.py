@@ -79,6 +79,10 @@ _SIGNATURES = {
                          ctypes.POINTER(ctypes.c_double)],
     "pmp_backward": [_P, _P, _P],
     "pmp_get_layout": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "pmp_get_path_prices": [_P, _P],
+    "pmp_prune_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "pmp_prune": [_P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P,
+                  ctypes.POINTER(ctypes.c_int64)],
     "pmp_destroy": [_P],
 }
 
@@ -127,7 +131,20 @@ def params_default(**overrides) -> pmp_params:
 
 
 def _device_array(torch, a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(dtype=dtype, device=device).contiguous()
     return torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dtype, device=device)
+
+
+class PrunedInstance:
+    """A problem whose arrays are device tensors (the output of pruning)."""
+
+    def __init__(self, m, n, row_ptr, col_idx, c, w, utility, lo, hi):
+        self.m, self.n = m, n
+        self.row_ptr, self.col_idx = row_ptr, col_idx
+        self.c, self.w, self.utility = c, w, utility
+        self.lo, self.hi = lo, hi
+        self.nnz = int(col_idx.numel())
 
 
 class Solver:
@@ -148,6 +165,7 @@ class Solver:
         self.device = torch.device(device)
         self.m, self.n = int(inst.m), int(inst.n)
         self.nnz = int(inst.row_ptr[-1])
+        self.lo, self.hi = float(inst.lo), float(inst.hi)
         npdt = np.float32 if self.dtype == torch.float32 else np.float64
         self.params = params or params_default(**kw)
         dt = PMP_F32 if self.dtype == torch.float32 else PMP_F64
@@ -224,6 +242,49 @@ class Solver:
     def update_capacity(self, c_new):
         c = self.torch.as_tensor(c_new).to(dtype=self.dtype, device=self.device).contiguous()
         _check(self.lib.pmp_update_capacity(self.handle, c.data_ptr()), "pmp_update_capacity")
+
+    def path_prices(self):
+        """pi[n] = sum of the link prices rho u along each route (Section VI-B)."""
+        pi = self.torch.empty(max(1, self.n), dtype=self.dtype, device=self.device)
+        _check(self.lib.pmp_get_path_prices(self.handle, pi.data_ptr()), "pmp_get_path_prices")
+        return pi[:self.n]
+
+    def prune(self, failed, params=None):
+        """Link failure (Section V-D): drop the links flagged in failed[m] and
+        every stream routed over one of them, on the device.  Returns
+        (solver of the pruned instance warm-started from this iterate,
+        link_map, stream_map) with the maps giving old indices; the pruned
+        problem's device arrays are kept as `solver.instance`."""
+        t = self.torch
+        f = t.as_tensor(failed).to(dtype=t.uint8, device=self.device).contiguous()
+        if f.numel() != self.m:
+            raise ValueError(f"failed must have m = {self.m} entries")
+        nb = ctypes.c_size_t()
+        _check(self.lib.pmp_prune_workspace_size(self.handle, ctypes.byref(nb)),
+               "pmp_prune_workspace_size")
+        ws = t.empty(max(1, nb.value), dtype=t.uint8, device=self.device)
+        i32 = dict(dtype=t.int32, device=self.device)
+        row_ptr = t.empty(self.m + 1, **i32)
+        col_idx = t.empty(max(1, self.nnz), **i32)
+        c = t.empty(self.m, dtype=self.dtype, device=self.device)
+        w = t.empty(max(1, self.n), dtype=self.dtype, device=self.device)
+        util = t.empty(max(1, self.n), dtype=t.uint8, device=self.device)
+        link_map = t.empty(self.m, **i32)
+        stream_map = t.empty(max(1, self.n), **i32)
+        state = t.empty(self.state_size(), dtype=t.uint8, device=self.device)
+        sizes = (ctypes.c_int64 * 3)()
+        _check(self.lib.pmp_prune(self.handle, f.data_ptr(), ws.data_ptr(), nb.value,
+                                  row_ptr.data_ptr(), col_idx.data_ptr(), c.data_ptr(),
+                                  w.data_ptr(), util.data_ptr(), link_map.data_ptr(),
+                                  stream_map.data_ptr(), state.data_ptr(), sizes), "pmp_prune")
+        m2, n2, nnz2 = (int(v) for v in sizes)
+        pruned = PrunedInstance(m2, n2, row_ptr[:m2 + 1], col_idx[:nnz2], c[:m2], w[:n2],
+                                util[:n2], self.lo, self.hi)
+        solver = Solver(pruned, dtype=self.dtype, params=params or self.params,
+                        device=self.device)
+        solver.instance = pruned
+        solver.set_state(state)
+        return solver, link_map[:m2], stream_map[:n2]
 
     def update_params(self, **kw):
         for k, v in kw.items():
