@@ -20,6 +20,9 @@ those workloads:
   paper    the scaling shape of Section V-B: n=m/2, route length U{5..15}
   batched  64 transit-style instances (line network x 48 time bins, trips on
            consecutive segment-time links), capacities degraded on 10% of links
+  transit_case_study  Section VI's time-expanded network at its sizes:
+           100 stations, 952 directed edges x 192 bins = 182,784 links,
+           110 OD pairs x 2 routes x 90 departures = 19,800 streams, w = 1
 
 Every route consists of distinct links (R is a 0/1 matrix, eq. (1)).
 """
@@ -199,6 +202,96 @@ def transit_instance(rng, m_target, T=48, len_lo=2, len_hi=12, n_per_link=5,
     w = rng.uniform(0.5, 2.0, n)
     utility = np.full(n, LOG, dtype=np.uint8)
     return Instance(name, m, n, row_ptr, col_idx, c, w, utility, 0.0, float(c.max()))
+
+
+def transit_case_study(seed=8, stations=100, T=192, edges=952, od_pairs=110,
+                       routes_per_od=2, departures=90, cap_lo=20.0, cap_hi=60.0):
+    """Section VI's time-expanded transit network at its stated size.
+
+    Stations are random points in the unit square.  The spatial network is
+    the minimum spanning tree of the complete distance graph plus the shortest
+    remaining station pairs until `edges` directed edges (both directions of
+    each pair) exist.  A link is an (edge, time bin) pair with index e*T + t;
+    every edge takes one bin.  An OD pair gets `routes_per_od` spatial routes:
+    the shortest path by length, then shortest paths with the edges already
+    used penalised 3x (so the alternatives differ where the network allows).
+    A stream j = (OD pair, route, departure t0) with t0 = 0..departures-1
+    uses links (e_k, t0 + k) along its route; w_j = 1 log utilities; seat
+    capacities U[cap_lo, cap_hi].  The defaults give m = 952 x 192 = 182,784
+    links and n = 110 x 2 x 90 = 19,800 streams, the sizes of Section VI's
+    case study (whose exact network the paper does not give).
+
+    Returns (Instance, meta) where meta holds per-stream od, route, t0 arrays
+    and the spatial routes as lists of edge indices."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra, minimum_spanning_tree
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((stations, 2))
+    dist = np.sqrt(((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1))
+    mst = minimum_spanning_tree(csr_matrix(dist)).tocoo()
+    pairs = {(min(a, b), max(a, b)) for a, b in zip(mst.row.tolist(), mst.col.tolist())}
+    iu, ju = np.triu_indices(stations, 1)
+    for k in np.argsort(dist[iu, ju], kind="stable"):
+        if len(pairs) * 2 >= edges:
+            break
+        pairs.add((int(iu[k]), int(ju[k])))
+    und = sorted(pairs)
+    src = np.array([a for a, b in und] + [b for a, b in und], dtype=np.int64)
+    dst = np.array([b for a, b in und] + [a for a, b in und], dtype=np.int64)
+    E = src.size
+    if E != edges:
+        raise ValueError("edge count not reachable")
+    eid = {(int(a), int(b)): e for e, (a, b) in enumerate(zip(src, dst))}
+    length = dist[src, dst]
+
+    def shortest(o, d, weight):
+        g = csr_matrix((weight, (src, dst)), shape=(stations, stations))
+        _, pred = dijkstra(g, indices=o, return_predecessors=True)
+        path, v = [], d
+        while v != o:
+            u = int(pred[v])
+            path.append(eid[(u, v)])
+            v = u
+        return path[::-1]
+
+    od = []
+    while len(od) < od_pairs:
+        o, d = (int(v) for v in rng.choice(stations, 2, replace=False))
+        if (o, d) not in od:
+            od.append((o, d))
+    routes = []
+    for o, d in od:
+        weight = length.copy()
+        rs = []
+        for _ in range(routes_per_od):
+            r = shortest(o, d, weight)
+            rs.append(r)
+            weight[r] *= 3.0
+        routes.append(rs)
+    longest = max(len(r) for rs in routes for r in rs)
+    if departures + longest > T:
+        raise ValueError("departures do not fit the time horizon")
+    links, streams, meta_od, meta_r, meta_t0 = [], [], [], [], []
+    j = 0
+    for k, rs in enumerate(routes):
+        for ri, r in enumerate(rs):
+            r_arr = np.asarray(r, dtype=np.int64)
+            for t0 in range(departures):
+                links.append(r_arr * T + t0 + np.arange(r_arr.size))
+                streams.append(np.full(r_arr.size, j, dtype=np.int64))
+                meta_od.append(k)
+                meta_r.append(ri)
+                meta_t0.append(t0)
+                j += 1
+    m, n = E * T, j
+    row_ptr, col_idx = csr_from_pairs(m, n, np.concatenate(links), np.concatenate(streams))
+    c = rng.uniform(cap_lo, cap_hi, m)
+    inst = Instance("transit_case_study", m, n, row_ptr, col_idx, c, np.ones(n),
+                    np.full(n, LOG, dtype=np.uint8), 0.0, float(c.max()))
+    meta = {"od": np.asarray(meta_od), "route": np.asarray(meta_r), "t0": np.asarray(meta_t0),
+            "routes": routes, "od_pairs": od, "edge_src": src, "edge_dst": dst, "T": T}
+    return inst, meta
 
 
 def batched(seed=3, count=64, m_lo=1e3, m_hi=1e5, scale=1.0):

@@ -78,3 +78,33 @@ def test_congested_adds_dense_rows():
     rows_c = np.repeat(np.arange(c.m), np.diff(c.row_ptr))
     orig = set((rows * base.n + base.col_idx).tolist())
     assert orig <= set((rows_c * c.n + c.col_idx).tolist())
+
+
+def test_transit_case_study_sizes_and_routes():
+    inst, meta = I.transit_case_study()
+    _check_pattern(inst)
+    assert (inst.m, inst.n) == (182784, 19800)       # Section VI's sizes
+    T, src, dst = meta["T"], meta["edge_src"], meta["edge_dst"]
+    assert src.size * T == inst.m
+    # each edge has its reverse; no self loops
+    assert set(zip(src.tolist(), dst.tolist())) == set(zip(dst.tolist(), src.tolist()))
+    assert np.all(src != dst)
+    for (o, d), rs in zip(meta["od_pairs"], meta["routes"]):
+        for r in rs:
+            # a path from o to d along existing edges
+            assert src[r[0]] == o and dst[r[-1]] == d
+            assert all(dst[a] == src[b] for a, b in zip(r[:-1], r[1:]))
+    # stream j uses (e_k, t0 + k) along its route, one time bin per edge
+    rows = np.repeat(np.arange(inst.m), np.diff(inst.row_ptr))
+    for j in (0, 1, 4321, inst.n - 1):
+        links = np.sort(rows[inst.col_idx == j])
+        r = meta["routes"][meta["od"][j]][meta["route"][j]]
+        want = np.sort(np.asarray(r) * T + meta["t0"][j] + np.arange(len(r)))
+        assert np.array_equal(links, want)
+    assert np.all(inst.w == 1.0) and np.all(inst.utility == I.LOG)
+
+
+def test_transit_case_study_small():
+    inst, meta = I.transit_case_study(stations=12, T=16, edges=30, od_pairs=6, departures=4)
+    _check_pattern(inst)
+    assert inst.m == 30 * 16 and inst.n == 6 * 2 * 4
