@@ -16,10 +16,13 @@
 //   link workgroup p: add its mx entries into FP64 LDS sums by local link
 //     index (lix), run the link epilogue (slack prox, average, dual update),
 //     then write v_l into mv tile by tile.
-// The LDS sums are FP64 atomic adds of FP32 messages; when the addends of one
-// sum span less than 2^24 in magnitude every partial sum is exact, so the
-// result does not depend on the order of the adds and equals the sequential
-// FP64 sum of the CSR/CSC kernels.
+// The LDS sums are FP64 atomic adds of FP32 messages.  Every addend is a
+// multiple of the smallest addend's FP32 ulp u, so while a sum stays below
+// 2^53 u every partial sum is exact (for example up to 32 addends spanning
+// less than 2^24 in magnitude, or 1000 spanning less than 2^19): the result
+// then does not depend on the order of the adds and equals the sequential
+// FP64 sum of the CSR/CSC kernels.  Beyond that the order of the adds moves
+// the last bits only.
 #include "pmp_device.h"
 
 #include <algorithm>
@@ -82,16 +85,53 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
 
 namespace {
 
+typedef double acc_t;   // LDS sums
+
+// Tuning knobs (defaults measured on MI355X at the large size and on a
+// congested instance):
+//   PMP_BIN_RUNS    merge runs of one link index before the LDS adds
+//   PMP_BIN_EMIT_U  tiles a wave emits per step
+//   PMP_BIN_EPI     rows per lane whose epilogue inputs are loaded before
+//                   any of them is updated
+#ifndef PMP_BIN_RUNS
+#define PMP_BIN_RUNS true
+#endif
+#ifndef PMP_BIN_EMIT_U
+#define PMP_BIN_EMIT_U 4
+#endif
+#ifndef PMP_BIN_EPI
+#define PMP_BIN_EPI 2
+#endif
+
+// Workgroups are handed to the 8 XCDs of the chip in turn (block b to XCD
+// b mod 8).  Renumbered so that every XCD runs one contiguous range of
+// blocks, neighbouring blocks write neighbouring tiles from the same L2, where
+// the partly written cache lines at tile boundaries merge before write-back.
+#ifndef PMP_BIN_XCD
+#define PMP_BIN_XCD 1
+#endif
+__device__ __forceinline__ int xcd_block(int b, int nblocks)
+{
+    if (!PMP_BIN_XCD) return b;
+    constexpr int X = 8;
+    const int x = b % X, per = nblocks / X, rem = nblocks % X;
+    return x * per + min(x, rem) + b / X;
+}
+
 // Add messages msg[e0..e1) into acc[idx[e]] (FP64 LDS atomics).  FP32
 // messages are read four at a time (16-byte message and 8-byte index loads,
 // aligned; the arrays carry 4 entries of padding), entries outside
 // [e0, e1) being masked.
-#ifndef PMP_BIN_ACC
-#define PMP_BIN_ACC double
-#endif
-typedef PMP_BIN_ACC acc_t;
-
-template <typename T>
+//
+// RUNS (link side): inside a tile the x messages are in CSR order, so a link
+// with many streams in the tile (a congested link) makes a long run of one
+// local index, and its LDS adds would all hit one address.  When some lane's
+// four entries share one index, the wave merges runs first: such a lane
+// contributes the sum of its four entries, a segmented sum over the lanes
+// (segments = maximal runs of equal indices) totals each run, and the last
+// lane of a run adds it once.  The sums are FP64 sums of FP32 messages, exact
+// under the same condition as the LDS adds, so the result does not change.
+template <typename T, bool RUNS>
 __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
                                            const uint16_t *__restrict__ idx, int e0, int e1,
                                            acc_t *acc)
@@ -101,14 +141,51 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
         typedef unsigned short u4 __attribute__((ext_vector_type(4)));
         const f4 *m4 = (const f4 *)msg;
         const u4 *i4 = (const u4 *)idx;
-        for (int b = (e0 >> 2) + threadIdx.x; b < ((e1 + 3) >> 2); b += kBinThreads) {
-            const f4 v = __builtin_nontemporal_load(m4 + b);
-            const u4 k = __builtin_nontemporal_load(i4 + b);
-            const int e = b << 2;
+        const int lane = threadIdx.x & 63;
+        auto add4 = [&](const f4 &v, const u4 &k, int e) {
             if (e >= e0 && e < e1) unsafeAtomicAdd(&acc[k.x], (acc_t)v.x);
             if (e + 1 >= e0 && e + 1 < e1) unsafeAtomicAdd(&acc[k.y], (acc_t)v.y);
             if (e + 2 >= e0 && e + 2 < e1) unsafeAtomicAdd(&acc[k.z], (acc_t)v.z);
             if (e + 3 >= e0 && e + 3 < e1) unsafeAtomicAdd(&acc[k.w], (acc_t)v.w);
+        };
+        // every lane of a wave takes the same trips (the run merge below is
+        // wave-wide); a lane past the end loads nothing
+        const int b1 = (e1 + 3) >> 2;
+        for (int bw = (e0 >> 2) + (threadIdx.x & ~63); bw < b1; bw += kBinThreads) {
+            const int b = bw + lane;
+            const bool in = b < b1;
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+            u4 k = {0, 0, 0, 0};
+            if (in) {
+                v = __builtin_nontemporal_load(m4 + b);
+                k = __builtin_nontemporal_load(i4 + b);
+            }
+            const int e = b << 2;
+            if constexpr (RUNS) {
+                const bool uni = in && e >= e0 && e + 3 < e1 && k.x == k.y && k.y == k.z &&
+                                 k.z == k.w;
+                if (__ballot(uni) != 0) {
+                    int key = uni ? (int)k.x : -1 - lane;   // others: segments of their own
+                    double sum = uni ? ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w)
+                                     : 0.0;
+                    if (in && !uni) add4(v, k, e);
+                    const int prev = __shfl_up(key, 1, 64);
+                    int head = lane == 0 || prev != key;
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const double so = __shfl_up(sum, off, 64);
+                        const int ho = __shfl_up(head, off, 64);
+                        if (lane >= off) {
+                            if (!head) sum += so;
+                            head |= ho;
+                        }
+                    }
+                    const int next = __shfl_down(key, 1, 64);
+                    if (uni && (lane == 63 || next != key)) unsafeAtomicAdd(&acc[key], (acc_t)sum);
+                    continue;
+                }
+            }
+            if (in) add4(v, k, e);
         }
     } else {
         for (int e = e0 + threadIdx.x; e < e1; e += kBinThreads)
@@ -122,7 +199,7 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
 // time: every lane loads the local indices of its entries in all four tiles
 // (up to two entries per tile) before any value is looked up and stored, so
 // eight index loads per lane are in flight; entries of longer tiles follow in
-// a tail loop.
+// rounds of four 64-entry chunks, again with the loads issued first.
 //   src_off[t], src_off[t + 1]   tile t in the read layout (index array idx)
 //   dst_off[t * dst_stride]      tile t in the written layout
 template <typename T>
@@ -132,7 +209,7 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
                                            const acc_t *vals, T *__restrict__ out)
 {
     constexpr int W = kBinThreads / 64;
-    constexpr int U = 4;
+    constexpr int U = PMP_BIN_EMIT_U;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int mine = ntiles > wave ? (ntiles - wave + W - 1) / W : 0;   // tiles of this wave
     for (int base = 0; base < mine; base += 64) {
@@ -166,43 +243,85 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
 #pragma unroll
                 for (int r = 0; r < 2; ++r)
                     if (id[u][r] >= 0) out[d_u[u] + lane + 64 * r] = (T)vals[id[u][r]];
+            // long tiles: four chunks of 64 entries per round, loads first
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                for (int k = lane + 128; k < c_u[u]; k += 64)
-                    out[d_u[u] + k] = (T)vals[idx[s_u[u] + k]];
+                for (int k0 = lane + 128; k0 - lane < c_u[u]; k0 += 256) {
+                    int it[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int k = k0 + 64 * r;
+                        it[r] = k < c_u[u] ? (int)idx[s_u[u] + k] : -1;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (it[r] >= 0) out[d_u[u] + k0 + 64 * r] = (T)vals[it[r]];
+                }
         }
     }
 }
 
+// Two workgroups of kBinThreads share a CU (the LDS sums fit twice): ask for
+// the register budget of 8 waves per SIMD.
+#ifndef PMP_BIN_WAVES
+#define PMP_BIN_WAVES 8
+#endif
+#if PMP_BIN_WAVES > 0
+#define PMP_BIN_KERNEL \
+    __global__ __launch_bounds__(kBinThreads) __attribute__((amdgpu_waves_per_eu(PMP_BIN_WAVES)))
+#else
+#define PMP_BIN_KERNEL __global__ __launch_bounds__(kBinThreads)
+#endif
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
+PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
 {
     if (d.ctl->done) return;
     extern __shared__ acc_t S[];
     __shared__ double sred[kBinThreads / 64];
-    const int q = blockIdx.x;
+    const int q = xcd_block(blockIdx.x, gridDim.x);
     const int j0 = q * d.SB;
     const int ns = min(d.SB, d.n - j0);
     for (int i = threadIdx.x; i < ns; i += kBinThreads) S[i] = 0.0;
     __syncthreads();
-    accumulate<T>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
+    accumulate<T, false>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
     __syncthreads();
     const double rho = d.ctl->rho;
     double part = 0.0;
-    for (int i = threadIdx.x; i < ns; i += kBinThreads) {
-        const int j = j0 + i;
-        const int L = d.col_ptr[j + 1] - d.col_ptr[j];
-        const double a = (double)d.a[j];
-        const T xt = (T)prox_stream((double)L * a + (double)S[i], L, (double)d.wsig[j], rho, d.lo, d.hi,
-                                    is_alpha2(d, j));
-        const double xn = (double)xt;
-        if (MODE == kCheck) {                  // dual residual: sum_j L_j (dx_j)^2
-            const double dx = xn - (double)d.x[j];
-            part += (double)L * dx * dx;
+    constexpr int G = PMP_BIN_EPI;
+    for (int i0 = threadIdx.x; i0 < ns; i0 += G * kBinThreads) {
+        int L[G];
+        double a[G], w[G], xo[G];
+        bool a2[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = i0 + g * kBinThreads;
+            if (i < ns) {
+                const int j = j0 + i;
+                L[g] = d.col_ptr[j + 1] - d.col_ptr[j];
+                a[g] = (double)d.a[j];
+                w[g] = (double)d.wsig[j];
+                a2[g] = is_alpha2(d, j);
+                xo[g] = MODE == kCheck ? (double)d.x[j] : 0.0;
+            }
         }
-        if (MODE != kPlain) d.x[j] = xt;       // otherwise x travels only in the messages
-        d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
-        S[i] = (acc_t)xn;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = i0 + g * kBinThreads;
+            if (i < ns) {
+                const int j = j0 + i;
+                const T xt = (T)prox_stream((double)L[g] * a[g] + (double)S[i], L[g], w[g], rho,
+                                            d.lo, d.hi, a2[g]);
+                const double xn = (double)xt;
+                if (MODE == kCheck) {          // dual residual: sum_j L_j (dx_j)^2
+                    const double dx = xn - xo[g];
+                    part += (double)L[g] * dx * dx;
+                }
+                if (MODE != kPlain) d.x[j] = xt;   // otherwise x travels only in the messages
+                d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a[g]);
+                S[i] = (acc_t)xn;
+            }
+        }
     }
     __syncthreads();
     // tile (q, p) of the v messages and tile (p, q) of the x messages list the
@@ -215,26 +334,44 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_stream(Dev<T> d)
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBinThreads) void k_bin_link(Dev<T> d)
+PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
 {
     if (d.ctl->done) return;
     extern __shared__ acc_t Y[];
     __shared__ double sred[kBinThreads / 64];
-    const int p = blockIdx.x;
+    const int p = xcd_block(blockIdx.x, gridDim.x);
     const int l0 = p * d.LB;
     const int nl = min(d.LB, d.m - l0);
     for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = 0.0;
     __syncthreads();
-    accumulate<T>(d.mx, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
+    accumulate<T, PMP_BIN_RUNS>(d.mx, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
     __syncthreads();
     double r2 = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < nl; i += kBinThreads) {
-        const int l = l0 + i;
-        const int deg = d.row_ptr[l + 1] - d.row_ptr[l];
-        // v goes out in the messages; a check stores it for k_bin_emit
-        const double y = (double)Y[i];
-        Y[i] = (acc_t)(MODE == kCheck ? link_update<T, MODE, true>(d, l, deg, y, r2, s2)
-                                      : link_update<T, MODE, false>(d, l, deg, y, r2, s2));
+    constexpr int G = PMP_BIN_EPI;
+    for (int i0 = threadIdx.x; i0 < nl; i0 += G * kBinThreads) {
+        int deg[G];
+        LinkIn in[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = i0 + g * kBinThreads;
+            if (i < nl) {
+                const int l = l0 + i;
+                deg[g] = d.row_ptr[l + 1] - d.row_ptr[l];
+                in[g] = link_load(d, l);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = i0 + g * kBinThreads;
+            if (i < nl) {
+                const int l = l0 + i;
+                // v goes out in the messages; a check stores it for k_bin_emit
+                const double y = (double)Y[i];
+                Y[i] = (acc_t)(MODE == kCheck
+                                   ? link_update_in<T, MODE, true>(d, l, deg[g], y, in[g], r2, s2)
+                                   : link_update_in<T, MODE, false>(d, l, deg[g], y, in[g], r2, s2));
+            }
+        }
     }
     if (MODE != kCheck) {
         __syncthreads();
@@ -254,10 +391,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_link(Dev<T> d)
 // are rewritten from v.  Runs also after the stop rule fired, so the
 // messages always match v.
 template <typename T>
-__global__ __launch_bounds__(kBinThreads) void k_bin_emit(Dev<T> d, int apply)
+PMP_BIN_KERNEL void k_bin_emit(Dev<T> d, int apply)
 {
     extern __shared__ acc_t Y[];
-    const int p = blockIdx.x;
+    const int p = xcd_block(blockIdx.x, gridDim.x);
     const int l0 = p * d.LB;
     const int nl = min(d.LB, d.m - l0);
     const double ratio = apply ? d.ctl->ratio : 1.0;

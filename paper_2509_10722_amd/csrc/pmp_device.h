@@ -118,12 +118,23 @@ __device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, d
     return part;
 }
 
-template <typename T, int MODE, bool WRITE_V = true>
-__device__ __forceinline__ double link_update(const Dev<T> &d, int l, int deg, double y,
-                                            double &r2, double &s2)
+// Per-link inputs of the link update, loaded ahead of it so that the loads
+// of several links can be in flight before any of their stores.
+struct LinkIn {
+    double c, u, b, zs;
+};
+
+template <typename T>
+__device__ __forceinline__ LinkIn link_load(const Dev<T> &d, int l)
 {
-    const double c = (double)d.c[l], u = (double)d.u[l];
-    const double b = (double)d.b[l], zs = (double)d.zs[l];
+    return LinkIn{(double)d.c[l], (double)d.u[l], (double)d.b[l], (double)d.zs[l]};
+}
+
+template <typename T, int MODE, bool WRITE_V = true>
+__device__ __forceinline__ double link_update_in(const Dev<T> &d, int l, int deg, double y,
+                                               const LinkIn &in, double &r2, double &s2)
+{
+    const double c = in.c, u = in.u, b = in.b, zs = in.zs;
     const double al = d.alpha;
     const double ps = fmax(zs - u, -c);                 // slack prox
     const double cnt = (double)deg + 1.0;               // |l| = d_l + 1
@@ -152,6 +163,13 @@ __device__ __forceinline__ double link_update(const Dev<T> &d, int l, int deg, d
         d.ps_prev[l] = ps;
     }
     return (double)vt;
+}
+
+template <typename T, int MODE, bool WRITE_V = true>
+__device__ __forceinline__ double link_update(const Dev<T> &d, int l, int deg, double y,
+                                            double &r2, double &s2)
+{
+    return link_update_in<T, MODE, WRITE_V>(d, l, deg, y, link_load(d, l), r2, s2);
 }
 
 // ---- residual reduction, stop rule and rho balancing ---------------------

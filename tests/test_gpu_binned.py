@@ -1,8 +1,8 @@
 """The binned message layout (PMP_LAYOUT_BINNED) against the gather layout
 and the FP64 oracle.
 
-The binned kernels add FP32 messages into FP64 LDS sums; when each sum's
-addends span less than 2^24 in magnitude every partial sum is exact and the
+The binned kernels add FP32 messages into FP64 LDS sums; while a sum stays
+below 2^53 ulps of its smallest addend every partial sum is exact and the
 result equals the gather layout's sequential FP64 sum bit for bit, which is
 the case on these instances.
 """
