@@ -44,7 +44,7 @@ constexpr int kSlots = 4;   // pipelined chunks in flight in pmp_solve
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t mx, mv, lix, six, ox, ov;
+    size_t mx, mv, lix, six, ox, ov, lbs, sbs;
     bool binned;
     BinnedPlan bp;
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
@@ -74,7 +74,7 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
     L.nlb_max = (int)std::min<long long>((long long)m, m / kBlock + 2 * nnz / kCap + 2);
     L.binned = use_binned(m, n, nnz, sz, layout);
     if (L.binned) {
-        L.bp = binned_plan(m, n);
+        L.bp = binned_plan(m, n);   // bounds; the blocks are cut at setup
         L.nsb_max = std::max(L.nsb_max, L.bp.Q);
         L.nlb_max = std::max(L.nlb_max, L.bp.P);
     }
@@ -117,6 +117,8 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
         L.six = take((size_t)(nnz + 4) * 2);
         L.ox = take(tiles * 4);
         L.ov = take(tiles * 4);
+        L.lbs = take(((size_t)L.bp.P + 1) * 4);
+        L.sbs = take(((size_t)L.bp.Q + 1) * 4);
     }
     L.total = off;
     return L;
@@ -363,11 +365,19 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     }
     d.binned = L.binned ? 1 : 0;
     if (L.binned) {
-        // tile offsets and local indices of the binned message layout
-        d.P = L.bp.P;
-        d.Q = L.bp.Q;
-        d.LB = L.bp.LB;
-        d.SB = L.bp.SB;
+        // blocks balanced by nonzeros, tile offsets and local indices of the
+        // binned message layout
+        BinnedPlan bp = L.bp;
+        std::vector<int> lbs((size_t)L.bp.P + 1), sbs((size_t)L.bp.Q + 1);
+        binned_blocks(hrow.data(), m, n, nnz, bp, lbs.data(), sbs.data());
+        if (bp.P > L.bp.P || bp.Q > L.bp.Q || bp.LB > L.bp.LB || bp.SB > L.bp.SB)
+            return fail(PMP_ERR_SHAPE, "internal: binned blocks exceed their bound");
+        d.P = bp.P;
+        d.Q = bp.Q;
+        d.LB = bp.LB;
+        d.SB = bp.SB;
+        d.lbs = (const int *)(ws + L.lbs);
+        d.sbs = (const int *)(ws + L.sbs);
         d.mx = (T *)(ws + L.mx);
         d.mv = (T *)(ws + L.mv);
         d.lix = (const uint16_t *)(ws + L.lix);
@@ -380,8 +390,10 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         HIP_TRY(hipStreamSynchronize(s));
         std::vector<int> ox(tiles), ov(tiles);
         std::vector<uint16_t> lix((size_t)nnz), six((size_t)nnz);
-        binned_build_host(hrow.data(), hcolidx.data(), m, n, L.bp, ox.data(), ov.data(), lix.data(),
-                          six.data());
+        binned_build_host(hrow.data(), hcolidx.data(), m, n, bp, lbs.data(), sbs.data(), ox.data(),
+                          ov.data(), lix.data(), six.data());
+        HIP_TRY(hipMemcpyAsync((void *)d.lbs, lbs.data(), ((size_t)d.P + 1) * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.sbs, sbs.data(), ((size_t)d.Q + 1) * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 4, hipMemcpyHostToDevice, s));
         if (nnz) {

@@ -30,32 +30,81 @@
 
 namespace pmp {
 
+namespace {
+
+// Count-based blocking: a multiple of 256 blocks (one or more per CU) of at
+// most kBinMaxBlock rows each.
+void split_by_count(int count, int &blocks, int &size)
+{
+    const long long per = 256LL * kBinMaxBlock;
+    const long long k = std::max<long long>(1, (count + per - 1) / per);
+    blocks = (int)(256 * k);
+    size = (int)std::max<long long>(1, (count + blocks - 1) / blocks);
+    blocks = (int)std::max<long long>(1, (count + size - 1) / size);
+}
+
+// Row cap of a balanced block: a quarter above the count-based size, within
+// kBinMaxBlock.
+int row_cap(int size) { return std::min(kBinMaxBlock, size + (size + 3) / 4); }
+
+// Close a block once it holds `quota` nonzeros or `cap` rows.  Blocks closed
+// by the quota number at most nnz / quota, blocks closed by the cap at most
+// count / cap, so there are at most blocks0 + count / cap + 1 of them.
+int cut_blocks(const int *ptr, int count, long long nnz, int blocks0, int cap, int *starts,
+               int &most)
+{
+    const long long quota = std::max<long long>(1, (nnz + blocks0 - 1) / blocks0);
+    int nb = 0, s = 0;
+    most = 0;
+    starts[0] = 0;
+    for (int i = 1; i <= count; ++i)
+        if (i == count || i - s >= cap || (long long)ptr[i] - ptr[s] >= quota) {
+            starts[++nb] = i;
+            most = std::max(most, i - s);
+            s = i;
+        }
+    return nb;
+}
+
+}  // namespace
+
 BinnedPlan binned_plan(int m, int n)
 {
-    // A multiple of 256 workgroups (one or more per CU) of at most
-    // kBinMaxBlock rows each.
-    auto split = [](int count, int &blocks, int &size) {
-        const long long per = 256LL * kBinMaxBlock;
-        const long long k = std::max<long long>(1, (count + per - 1) / per);
-        blocks = (int)(256 * k);
-        size = (int)std::max<long long>(1, (count + blocks - 1) / blocks);
-        blocks = (int)std::max<long long>(1, (count + size - 1) / size);
-    };
     BinnedPlan bp{};
-    split(m, bp.P, bp.LB);
-    split(n, bp.Q, bp.SB);
+    int p0, lb0, q0, sb0;
+    split_by_count(m, p0, lb0);
+    split_by_count(n, q0, sb0);
+    bp.LB = row_cap(lb0);
+    bp.P = p0 + (m + bp.LB - 1) / bp.LB + 1;
+    bp.SB = sb0;
+    bp.Q = q0;
     return bp;
 }
 
+void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &bp, int *lbs,
+                   int *sbs)
+{
+    int p0, lb0, q0, sb0;
+    split_by_count(m, p0, lb0);
+    split_by_count(n, q0, sb0);
+    // links: balanced by nonzeros (a congested link has thousands)
+    bp.P = cut_blocks(row_ptr, m, nnz, p0, row_cap(lb0), lbs, bp.LB);
+    // streams: by count (routes are short), so the block of stream j is j / SB
+    bp.Q = q0;
+    bp.SB = sb0;
+    for (int q = 0; q <= q0; ++q) sbs[q] = (int)std::min<long long>((long long)q * sb0, n);
+}
+
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
-                       int *ox, int *ov, uint16_t *lix, uint16_t *six)
+                       const int *lbs, const int *sbs, int *ox, int *ov, uint16_t *lix,
+                       uint16_t *six)
 {
     const long long P = bp.P, Q = bp.Q;
+    (void)n;
     std::vector<long long> cnt((size_t)(P * Q), 0);
-    for (int l = 0; l < m; ++l) {
-        const long long p = l / bp.LB;
-        for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) cnt[(size_t)(p * Q + col_idx[k] / bp.SB)]++;
-    }
+    for (long long p = 0; p < P; ++p)
+        for (int l = lbs[p]; l < lbs[p + 1]; ++l)
+            for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) cnt[(size_t)(p * Q + col_idx[k] / bp.SB)]++;
     long long acc = 0;   // < nnz < 2^31
     for (long long p = 0; p < P; ++p)
         for (long long q = 0; q < Q; ++q) {
@@ -71,16 +120,15 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
         }
     ov[Q * P] = (int)acc;
     std::fill(cnt.begin(), cnt.end(), 0);
-    for (int l = 0; l < m; ++l) {
-        const long long p = l / bp.LB;
-        for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) {
-            const int j = col_idx[k];
-            const long long q = j / bp.SB;
-            const long long r = cnt[(size_t)(p * Q + q)]++;   // rank in the tile, CSR order
-            lix[ox[p * Q + q] + r] = (uint16_t)(l - p * bp.LB);
-            six[ov[q * P + p] + r] = (uint16_t)(j - q * bp.SB);
-        }
-    }
+    for (long long p = 0; p < P; ++p)
+        for (int l = lbs[p]; l < lbs[p + 1]; ++l)
+            for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) {
+                const int j = col_idx[k];
+                const long long q = j / bp.SB;
+                const long long r = cnt[(size_t)(p * Q + q)]++;   // rank in the tile, CSR order
+                lix[ox[p * Q + q] + r] = (uint16_t)(l - lbs[p]);
+                six[ov[q * P + p] + r] = (uint16_t)(j - sbs[q]);
+            }
 }
 
 namespace {
@@ -280,8 +328,8 @@ PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
     extern __shared__ acc_t S[];
     __shared__ double sred[kBinThreads / 64];
     const int q = xcd_block(blockIdx.x, gridDim.x);
-    const int j0 = q * d.SB;
-    const int ns = min(d.SB, d.n - j0);
+    const int j0 = d.sbs[q];
+    const int ns = d.sbs[q + 1] - j0;
     for (int i = threadIdx.x; i < ns; i += kBinThreads) S[i] = 0.0;
     __syncthreads();
     accumulate<T, false>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
@@ -340,8 +388,8 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
     extern __shared__ acc_t Y[];
     __shared__ double sred[kBinThreads / 64];
     const int p = xcd_block(blockIdx.x, gridDim.x);
-    const int l0 = p * d.LB;
-    const int nl = min(d.LB, d.m - l0);
+    const int l0 = d.lbs[p];
+    const int nl = d.lbs[p + 1] - l0;
     for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = 0.0;
     __syncthreads();
     accumulate<T, PMP_BIN_RUNS>(d.mx, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
@@ -395,8 +443,8 @@ PMP_BIN_KERNEL void k_bin_emit(Dev<T> d, int apply)
 {
     extern __shared__ acc_t Y[];
     const int p = xcd_block(blockIdx.x, gridDim.x);
-    const int l0 = p * d.LB;
-    const int nl = min(d.LB, d.m - l0);
+    const int l0 = d.lbs[p];
+    const int nl = d.lbs[p + 1] - l0;
     const double ratio = apply ? d.ctl->ratio : 1.0;
     for (int i = threadIdx.x; i < nl; i += kBinThreads) {
         const int l = l0 + i;

@@ -94,10 +94,11 @@ struct Dev {
     double lo, hi, alpha;
     Ctl *ctl;
     HistEntry *hist;
-    // Binned message layout (pmp_binned.hip); P link blocks of LB links and
-    // Q stream blocks of SB streams tile R into P x Q tiles.
+    // Binned message layout (pmp_binned.hip); P link blocks of at most LB
+    // links and Q stream blocks of at most SB streams tile R into P x Q tiles.
     int binned;                     // 1: iterations use the binned kernels
     int P, Q, LB, SB;
+    const int *lbs, *sbs;           // [P+1], [Q+1] first link / stream of each block
     T *mx;                          // [nnz] stream -> link messages, tiles p-major
     T *mv;                          // [nnz] link -> stream messages, tiles q-major
     const uint16_t *lix;            // [nnz] local link of each mx entry
@@ -159,17 +160,26 @@ hipError_t prune_device(const Dev<T> &d, const uint8_t *failed, int *scratch, in
 #define PMP_BIN_THREADS 1024
 #endif
 #ifndef PMP_BIN_MAX_BLOCK
-#define PMP_BIN_MAX_BLOCK 10240
+#define PMP_BIN_MAX_BLOCK 10112   // two workgroups' FP64 sums fit one CU's 160 KiB LDS
 #endif
 constexpr int kBinThreads = PMP_BIN_THREADS;       // threads per binned workgroup
 constexpr int kBinMaxBlock = PMP_BIN_MAX_BLOCK;    // links / streams per binned workgroup
 struct BinnedPlan {
-    int P, Q, LB, SB;
+    int P, Q;     // link blocks, stream blocks
+    int LB, SB;   // most links / streams in one block (LDS sums per workgroup)
 };
+// Bounds of the plan from the sizes alone (workspace sizing).
 BinnedPlan binned_plan(int m, int n);
-// Host construction of ox, ov, lix, six from the CSR pattern.
+// Block boundaries lbs[P+1] of the links, balanced by nonzeros (a block
+// closes once it holds the nonzero quota or its row cap), and sbs[Q+1] of
+// the streams, by count (stream j is in block j / SB); sets P, Q, LB, SB of
+// bp to the actual values (within the bounds of binned_plan).
+void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &bp, int *lbs,
+                   int *sbs);
+// Host construction of ox, ov, lix, six from the CSR pattern and the blocks.
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
-                       int *ox, int *ov, uint16_t *lix, uint16_t *six);
+                       const int *lbs, const int *sbs, int *ox, int *ov, uint16_t *lix,
+                       uint16_t *six);
 // mode: kPlain (x stays in the messages), kSave (x also stored, for the
 // next iteration's check), kCheck (residual partials; x stored)
 template <typename T>
