@@ -99,3 +99,16 @@ def test_status_strings():
     lib = pmp.load_library()
     assert lib.pmp_status_string(0) == b"ok"
     assert lib.pmp_status_string(6) == b"not converged"
+
+
+def test_null_handles_are_rejected():
+    from paper_2509_10722_amd import pmp
+    lib = pmp.load_library()
+    b = ctypes.c_size_t()
+    sizes = (ctypes.c_int64 * 3)()
+    assert lib.pmp_get_path_prices(None, None) == pmp.PMP_ERR_INVALID
+    assert lib.pmp_prune_workspace_size(None, ctypes.byref(b)) == pmp.PMP_ERR_INVALID
+    assert lib.pmp_prune(None, None, None, 0, None, None, None, None, None, None, None, None,
+                         sizes) == pmp.PMP_ERR_INVALID
+    assert lib.pmp_state_size(None, ctypes.byref(b)) == pmp.PMP_ERR_INVALID
+    assert lib.pmp_last_error().decode()
