@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--tol-max-iter", type=int, default=20000)
     ap.add_argument("--no-tol", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--cpu-single-iters", type=int, default=1,
+                    help="iterations of the single-thread oracle run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "gather", "binned"])
     ap.add_argument("--pattern", default="plain",
@@ -469,6 +471,12 @@ def main():
                "cores": ro["threads"], "kind": "oracle",
                "sample": f"{k} iterations of the FP64 literal per-terminal oracle on the same "
                          f"{args.config} instance (setup excluded, {ro['loop_seconds']:.1f} s)"}
+        if args.cpu_single_iters > 0:
+            k1 = args.cpu_single_iters
+            r1 = oracle.run(inst32, k1, threads=1)
+            cpu["single_thread"] = {"value": round(k1 / r1["loop_seconds"], 4), "unit": "iter/s",
+                                    "sample": f"{k1} iterations on one thread "
+                                              f"({r1['loop_seconds']:.1f} s)"}
         log(f"[bench] cpu baseline: {cpu}")
 
     line = {
