@@ -44,7 +44,7 @@ constexpr int kSlots = 4;   // pipelined chunks in flight in pmp_solve
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t mx, mv, lix, six, ox, ov, lbs, sbs;
+    size_t mx, mv, lix, six, ox, ov, lbs, sbs, rlen, dlen;
     bool binned;
     BinnedPlan bp;
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
@@ -119,6 +119,8 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
         L.ov = take(tiles * 4);
         L.lbs = take(((size_t)L.bp.P + 1) * 4);
         L.sbs = take(((size_t)L.bp.Q + 1) * 4);
+        L.rlen = take((size_t)n);
+        L.dlen = take((size_t)m);
     }
     L.total = off;
     return L;
@@ -378,6 +380,25 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         d.SB = bp.SB;
         d.lbs = (const int *)(ws + L.lbs);
         d.sbs = (const int *)(ws + L.sbs);
+        // one byte per route length / link degree instead of two pointer
+        // reads, when they all fit
+        auto lengths = [&](const std::vector<int> &ptr, int count, size_t off,
+                           const uint8_t *&out) -> pmp_status {
+            std::vector<uint8_t> len((size_t)count);
+            out = nullptr;
+            for (int i = 0; i < count; ++i) {
+                const int v = ptr[(size_t)i + 1] - ptr[(size_t)i];
+                if (v > 255) return PMP_OK;
+                len[(size_t)i] = (uint8_t)v;
+            }
+            HIP_TRY(hipMemcpyAsync(ws + off, len.data(), (size_t)count, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));   // len goes out of scope
+            out = (const uint8_t *)(ws + off);
+            return PMP_OK;
+        };
+        pmp_status ls = lengths(hcol, n, L.rlen, d.rlen);
+        if (ls == PMP_OK) ls = lengths(hrow, m, L.dlen, d.dlen);
+        if (ls != PMP_OK) return ls;
         d.mx = (T *)(ws + L.mx);
         d.mv = (T *)(ws + L.mv);
         d.lix = (const uint16_t *)(ws + L.lix);

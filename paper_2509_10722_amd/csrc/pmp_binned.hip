@@ -346,7 +346,7 @@ PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
             const int i = i0 + g * kBinThreads;
             if (i < ns) {
                 const int j = j0 + i;
-                L[g] = d.col_ptr[j + 1] - d.col_ptr[j];
+                L[g] = d.rlen ? (int)d.rlen[j] : d.col_ptr[j + 1] - d.col_ptr[j];
                 a[g] = (double)d.a[j];
                 w[g] = (double)d.wsig[j];
                 a2[g] = is_alpha2(d, j);
@@ -404,7 +404,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
             const int i = i0 + g * kBinThreads;
             if (i < nl) {
                 const int l = l0 + i;
-                deg[g] = d.row_ptr[l + 1] - d.row_ptr[l];
+                deg[g] = d.dlen ? (int)d.dlen[l] : d.row_ptr[l + 1] - d.row_ptr[l];
                 in[g] = link_load(d, l);
             }
         }

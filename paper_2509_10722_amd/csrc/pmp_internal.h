@@ -99,6 +99,8 @@ struct Dev {
     int binned;                     // 1: iterations use the binned kernels
     int P, Q, LB, SB;
     const int *lbs, *sbs;           // [P+1], [Q+1] first link / stream of each block
+    const uint8_t *rlen;            // [n] route lengths when all are below 256, else NULL
+    const uint8_t *dlen;            // [m] link degrees when all are below 256, else NULL
     T *mx;                          // [nnz] stream -> link messages, tiles p-major
     T *mv;                          // [nnz] link -> stream messages, tiles q-major
     const uint16_t *lix;            // [nnz] local link of each mx entry
