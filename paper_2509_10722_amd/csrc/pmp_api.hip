@@ -451,14 +451,15 @@ void link_pass(const Dev<T> &d, int mode, long long delta, int stop, hipStream_t
                                  stop, s);
 }
 
-// After a check iteration: the u rescale of a balancing step (gather layout:
-// only needed at balancing iterations; binned layout: always, since the
-// check link pass leaves the link messages to this step).
+// After a check iteration: the u rescale of a balancing step, which only
+// balancing iterations can need (the kernels return at once when rho did not
+// change); the binned layout then also rewrites its link messages.
 template <typename T>
 void after_check(const Dev<T> &d, bool adapt_iteration, hipStream_t s)
 {
+    if (!adapt_iteration) return;
     if (d.binned) launch_bin_emit<T>(d, 1, s);
-    else if (adapt_iteration) launch_rescale<T>(d, s);
+    else launch_rescale<T>(d, s);
 }
 
 // Refresh the link messages from v after v changed outside an iteration.

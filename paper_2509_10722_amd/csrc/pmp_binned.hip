@@ -395,7 +395,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
     accumulate<T, PMP_BIN_RUNS>(d.mx, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
     __syncthreads();
     double r2 = 0.0, s2 = 0.0;
-    constexpr int G = PMP_BIN_EPI;
+    constexpr int G = MODE == kCheck ? 1 : PMP_BIN_EPI;   // a check carries more inputs
     for (int i0 = threadIdx.x; i0 < nl; i0 += G * kBinThreads) {
         int deg[G];
         LinkIn in[G];
@@ -405,7 +405,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
             if (i < nl) {
                 const int l = l0 + i;
                 deg[g] = d.dlen ? (int)d.dlen[l] : d.row_ptr[l + 1] - d.row_ptr[l];
-                in[g] = link_load(d, l);
+                in[g] = link_load<T, MODE>(d, l);
             }
         }
 #pragma unroll
@@ -413,7 +413,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
             const int i = i0 + g * kBinThreads;
             if (i < nl) {
                 const int l = l0 + i;
-                // v goes out in the messages; a check stores it for k_bin_emit
+                // v goes out in the messages; a check also stores it
                 const double y = (double)Y[i];
                 Y[i] = (acc_t)(MODE == kCheck
                                    ? link_update_in<T, MODE, true>(d, l, deg[g], y, in[g], r2, s2)
@@ -421,10 +421,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
             }
         }
     }
-    if (MODE != kCheck) {
-        __syncthreads();
-        emit_tiles<T>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, d.mv);
-    } else {
+    if (MODE == kCheck) {
         r2 = block_sum_n<kBinThreads>(r2, sred);
         s2 = block_sum_n<kBinThreads>(s2, sred);
         if (threadIdx.x == 0) {
@@ -432,15 +429,18 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
             d.lpart[2 * p + 1] = s2;
         }
     }
+    __syncthreads();
+    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, d.mv);
 }
 
 // After a check (apply = 1): apply a pending u rescale (eq. (7)), refresh
-// v = b - u and write the link messages.  With apply = 0 only the messages
-// are rewritten from v.  Runs also after the stop rule fired, so the
-// messages always match v.
+// v = b - u and rewrite the link messages; without a pending rescale the
+// check's link pass has written them already and nothing is done.  With
+// apply = 0 the messages are rewritten from v.
 template <typename T>
 PMP_BIN_KERNEL void k_bin_emit(Dev<T> d, int apply)
 {
+    if (apply && d.ctl->ratio == 1.0) return;
     extern __shared__ acc_t Y[];
     const int p = xcd_block(blockIdx.x, gridDim.x);
     const int l0 = d.lbs[p];

@@ -122,12 +122,18 @@ __device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, d
 // of several links can be in flight before any of their stores.
 struct LinkIn {
     double c, u, b, zs;
+    double yp, pp;   // saved y and ps of the previous iteration (checks only)
 };
 
-template <typename T>
+template <typename T, int MODE>
 __device__ __forceinline__ LinkIn link_load(const Dev<T> &d, int l)
 {
-    return LinkIn{(double)d.c[l], (double)d.u[l], (double)d.b[l], (double)d.zs[l]};
+    LinkIn in{(double)d.c[l], (double)d.u[l], (double)d.b[l], (double)d.zs[l], 0.0, 0.0};
+    if (MODE == kCheck) {
+        in.yp = d.y_prev[l];
+        in.pp = d.ps_prev[l];
+    }
+    return in;
 }
 
 template <typename T, int MODE, bool WRITE_V = true>
@@ -152,7 +158,7 @@ __device__ __forceinline__ double link_update_in(const Dev<T> &d, int l, int deg
         // sum_{j on l} (Dx_j - Dpbar)^2 + (Dps - Dpbar)^2
         //   = [sum_j Dx_j^2] + d Dpbar^2 - 2 Dpbar Dy + (Dps - Dpbar)^2,
         // the bracket being added on the stream side.
-        const double yp = d.y_prev[l], pp = d.ps_prev[l];
+        const double yp = in.yp, pp = in.pp;
         const double dpb = pbar - (yp + pp) / cnt;
         const double dy = y - yp, dps = ps - pp;
         r2 += cnt * pbar * pbar;
@@ -169,7 +175,7 @@ template <typename T, int MODE, bool WRITE_V = true>
 __device__ __forceinline__ double link_update(const Dev<T> &d, int l, int deg, double y,
                                             double &r2, double &s2)
 {
-    return link_update_in<T, MODE, WRITE_V>(d, l, deg, y, link_load(d, l), r2, s2);
+    return link_update_in<T, MODE, WRITE_V>(d, l, deg, y, link_load<T, MODE>(d, l), r2, s2);
 }
 
 // ---- residual reduction, stop rule and rho balancing ---------------------
