@@ -367,8 +367,8 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     }
     d.binned = L.binned ? 1 : 0;
     if (L.binned) {
-        // blocks balanced by nonzeros, tile offsets and local indices of the
-        // binned message layout
+        // link blocks balanced by nonzeros, stream blocks by count; tile
+        // offsets and local indices of the binned message layout
         BinnedPlan bp = L.bp;
         std::vector<int> lbs((size_t)L.bp.P + 1), sbs((size_t)L.bp.Q + 1);
         binned_blocks(hrow.data(), m, n, nnz, bp, lbs.data(), sbs.data());

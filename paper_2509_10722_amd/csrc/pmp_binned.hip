@@ -5,8 +5,9 @@
 // from an 80 MB vector run an order of magnitude below streaming bandwidth.
 // This layout instead moves one message per nonzero through HBM in
 // coalesced runs:
-//   R is tiled into P x Q tiles (link block p of LB links, stream block q of
-//   SB streams).  mx holds x_j for every nonzero, tile by tile in p-major
+//   R is tiled into P x Q tiles (link block p: consecutive links holding
+//   about nnz / P nonzeros, at most LB links; stream block q: SB consecutive
+//   streams).  mx holds x_j for every nonzero, tile by tile in p-major
 //   order; mv holds v_l in q-major order; both list a tile's nonzeros in the
 //   same order (CSR order), so entry k of tile (p, q) is the same nonzero in
 //   both.
