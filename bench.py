@@ -117,6 +117,8 @@ def bench_batched(args, log):
         "time_s": round(tb, 4), "plain_time_s": round(tp, 4),
         "speedup_vs_plain": round(tp / tb, 3), "converged": conv,
         "iterations_equal_plain": sum(int(a == c) for a, c in zip(iters, plain_iters)),
+        "iterations": {"min": int(min(iters)), "median": int(np.median(iters)),
+                       "max": int(max(iters))},
         "model_gbs": round(work / tb / 1e9, 2),
     }
     print(json.dumps(line), flush=True)

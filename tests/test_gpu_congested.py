@@ -1,6 +1,7 @@
 """Congested links (Section V-C): rows far longer than one workgroup's LDS
 stage are summed by several workgroups in chunks and finished by a second
-kernel in chunk order."""
+kernel in chunk order (gather layout); the binned layout balances its link
+blocks by nonzeros and merges runs of one link in its LDS sums."""
 import numpy as np
 import pytest
 
@@ -14,7 +15,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_2509_10722_amd.pmp import Solver  # noqa: E402
+from paper_2509_10722_amd.pmp import PMP_LAYOUT_BINNED, PMP_LAYOUT_GATHER, Solver  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -28,11 +29,13 @@ def test_congested_rows_are_long(congested):
     assert (deg > 8192).sum() >= 10            # several chunks per long row
 
 
+@pytest.mark.parametrize("layout", [PMP_LAYOUT_GATHER, PMP_LAYOUT_BINNED])
 @pytest.mark.parametrize("dtype_name,tol", [("float64", 1e-10), ("float32", 1e-5)])
-def test_congested_equal_iterations(congested, dtype_name, tol):
+def test_congested_equal_iterations(congested, dtype_name, tol, layout):
     inst = congested if dtype_name == "float64" else congested.rounded(np.float32)
     K = 120
-    s = Solver(inst, dtype=getattr(torch, dtype_name))
+    s = Solver(inst, dtype=getattr(torch, dtype_name), layout=layout)
+    assert s.layout_in_use() == ("binned" if layout == PMP_LAYOUT_BINNED else "gather")
     s.iterate(K)
     r, sn, _ = s.residuals()
     x, lam, _ = s.solution()
@@ -44,9 +47,12 @@ def test_congested_equal_iterations(congested, dtype_name, tol):
 
 
 def test_congested_solve_deterministic(congested):
+    # gather layout: fixed-order sums (the binned layout's LDS adds of a
+    # congested link's 10^4 messages need not be exact, so their order may
+    # show in the last bits)
     res = []
     for _ in range(2):
-        s = Solver(congested, dtype=torch.float32)
+        s = Solver(congested, dtype=torch.float32, layout=PMP_LAYOUT_GATHER)
         r = s.solve()
         x, lam, _ = s.solution()
         res.append((r["iterations"], host(x), host(lam)))
