@@ -279,11 +279,11 @@ typedef struct {
     int32_t tile_cap[3];
     int32_t reorder_streams;
     int32_t wg_per_cu;      /* resident workgroups per CU in the persistent grid
-                               (1..8, capped by occupancy; 0 = 4) */
+                               (1..8, capped by occupancy; 0 = 2) */
 } pmp_batch_options;
 
-/* Defaults: classes at m = 1e4 and 5e4, tile caps 1024 / 2048 / 4096,
- * reorder_streams 1, wg_per_cu 4. */
+/* Defaults (tuned on MI355X for transit batches): classes at m = 1e4 and
+ * 5e4, tile caps 4096 for every class, reorder_streams 1, wg_per_cu 2. */
 pmp_status pmp_batch_options_default(pmp_batch_options *options);
 pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,
                                     const pmp_params *params, const pmp_batch_options *options,

@@ -259,7 +259,7 @@ int batch_grid_size(int device, int want_per_cu)
         return 0;
     // a few resident workgroups per CU: enough to cover latency, few enough to
     // keep the grid barriers short (tunable)
-    return std::min(per_cu, want_per_cu > 0 ? want_per_cu : 4) * cus;
+    return std::min(per_cu, want_per_cu > 0 ? want_per_cu : 2) * cus;
 }
 
 template void launch_batch_gather_x<float>(const float *, const int *, int, float *, hipStream_t);
@@ -687,11 +687,12 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     if (!o) return set_error(PMP_ERR_INVALID, "options is NULL");
     o->class_m[0] = 10000;
     o->class_m[1] = 50000;
-    o->tile_cap[0] = 1024;
-    o->tile_cap[1] = 2048;
+    // the autotuner's choice on MI355X for the transit batch of Section VI
+    o->tile_cap[0] = 4096;
+    o->tile_cap[1] = 4096;
     o->tile_cap[2] = 4096;
     o->reorder_streams = 1;
-    o->wg_per_cu = 4;
+    o->wg_per_cu = 2;
     return PMP_OK;
 }
 
