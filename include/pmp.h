@@ -104,8 +104,8 @@ typedef struct {
  *   check_every  residual / stop-test period of pmp_solve (>= 1)
  *   max_iter     iteration cap of one pmp_solve call
  *   layout       sparse layout of the iteration: PMP_LAYOUT_AUTO picks
- *                PMP_LAYOUT_BINNED for FP32 problems with nnz >= 2^24 and
- *                PMP_LAYOUT_GATHER otherwise.  GATHER: CSR / CSC passes with
+ *                PMP_LAYOUT_BINNED for FP32 problems with nnz >= 2^21 and
+ *                m, n >= 256, PMP_LAYOUT_GATHER otherwise.  GATHER: CSR / CSC passes with
  *                LDS-staged gathers.  BINNED: R tiled into link-block x
  *                stream-block tiles with one FP32 message per nonzero per
  *                direction, streamed through HBM in coalesced runs (for
