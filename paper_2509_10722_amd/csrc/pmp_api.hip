@@ -662,18 +662,20 @@ pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
     hipStream_t st = h->stream;
     pmp_status rc;
     launch_ctl_clear_done(h->ctl, st);
-    launch_refresh_v<T>(d, st);   // the binned layout keeps v in its messages between checks
+    // v from (b, u), and the binned layout's link messages from v (between
+    // checks that layout keeps v in its messages only)
+    launch_refresh_v<T>(d, st);
+    refresh_messages<T>(d, st);
     for (int t = 1; t <= K; ++t) {
         if ((t - 1) % s == 0)
             if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)((t - 1) / s) * L.state, true)) != PMP_OK)
                 return rc;
-        launch_stream_pass<T>(d, false, st);
-        launch_link_pass<T>(d, kPlain, st);
+        stream_pass<T>(d, t == K ? kSave : kPlain, st);   // x^K stored
+        link_pass<T>(d, kPlain, 0, 0, st);
     }
     h->iter_enq += K;
     if ((rc = copy_state<T>(h, ws + L.final_state, true)) != PMP_OK) return rc;
     if (h->n) HIP_TRY(hipMemcpyAsync(ws + L.xK, d.x, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
-    refresh_messages<T>(d, st);
     launch_objective<T>(d, (double *)(ws + L.part), L.nobj, (double *)(ws + L.J), st);
     HIP_TRY(hipGetLastError());
     double jv = 0.0;
@@ -706,13 +708,14 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
     for (int seg = L.nck - 1; seg >= 0; --seg) {
         const int t0 = seg * s, t1 = std::min(t0 + s, K);
         if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)seg * L.state, false)) != PMP_OK) return rc;
+        refresh_messages<T>(d, st);
         for (int t = t0 + 1; t <= t1; ++t) {            // recompute, recording x^t and mu^t
-            launch_stream_pass<T>(d, false, st);
+            stream_pass<T>(d, kSave, st);               // kSave: x stored in both layouts
             if (h->n)
                 HIP_TRY(hipMemcpyAsync(tape_x + (size_t)(t - t0 - 1) * h->n, d.x,
                                        (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
             launch_slack_mask<T>(d, tape_mu + (size_t)(t - t0 - 1) * h->m, st);
-            launch_link_pass<T>(d, kPlain, st);
+            link_pass<T>(d, kPlain, 0, 0, st);
         }
         if (t1 < K)   // link step of iteration t1, deferred from the later segment
             launch_adj_link_only<T>(d, a, tape_mu + (size_t)(t1 - t0 - 1) * h->m, st);
