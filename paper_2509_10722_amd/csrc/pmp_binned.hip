@@ -27,6 +27,7 @@
 #include "pmp_device.h"
 
 #include <algorithm>
+#include <thread>
 #include <vector>
 
 namespace pmp {
@@ -101,11 +102,25 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
                        uint16_t *six)
 {
     const long long P = bp.P, Q = bp.Q;
+    (void)m;
     (void)n;
-    std::vector<long long> cnt((size_t)(P * Q), 0);
-    for (long long p = 0; p < P; ++p)
+    // Link block p touches only tiles (p, *) and their slots, so the counting
+    // and the placing passes split over link blocks across host threads.
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto over_blocks = [&](auto &&body) {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&, t] {
+                for (long long p = t; p < P; p += nth) body(p);
+            });
+        for (auto &th : pool) th.join();
+    };
+    std::vector<int> cnt((size_t)(P * Q), 0);
+    over_blocks([&](long long p) {
+        int *c = cnt.data() + p * Q;
         for (int l = lbs[p]; l < lbs[p + 1]; ++l)
-            for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) cnt[(size_t)(p * Q + col_idx[k] / bp.SB)]++;
+            for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) c[col_idx[k] / bp.SB]++;
+    });
     long long acc = 0;   // < nnz < 2^31
     for (long long p = 0; p < P; ++p)
         for (long long q = 0; q < Q; ++q) {
@@ -120,16 +135,18 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
             acc += cnt[(size_t)(p * Q + q)];
         }
     ov[Q * P] = (int)acc;
-    std::fill(cnt.begin(), cnt.end(), 0);
-    for (long long p = 0; p < P; ++p)
+    over_blocks([&](long long p) {
+        int *c = cnt.data() + p * Q;
+        std::fill(c, c + Q, 0);
         for (int l = lbs[p]; l < lbs[p + 1]; ++l)
             for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) {
                 const int j = col_idx[k];
                 const long long q = j / bp.SB;
-                const long long r = cnt[(size_t)(p * Q + q)]++;   // rank in the tile, CSR order
+                const int r = c[q]++;   // rank in the tile, CSR order
                 lix[ox[p * Q + q] + r] = (uint16_t)(l - lbs[p]);
                 six[ov[q * P + p] + r] = (uint16_t)(j - sbs[q]);
             }
+    });
 }
 
 namespace {
