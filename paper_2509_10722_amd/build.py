@@ -9,8 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libpmp.so")
-SOURCES = ["pmp_kernels.hip", "pmp_binned.hip", "pmp_adjoint.hip", "pmp_batch.hip", "pmp_prune.hip",
-           "pmp_api.hip"]
+SOURCES = ["pmp_kernels.hip", "pmp_binned.hip", "pmp_binned_plan.hip", "pmp_adjoint.hip",
+           "pmp_batch.hip", "pmp_prune.hip", "pmp_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

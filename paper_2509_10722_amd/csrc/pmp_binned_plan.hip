@@ -1,0 +1,129 @@
+// Host side of the binned layout: the blocking of links and streams and the
+// tile tables (offsets and local indices) built from the CSR pattern.  The
+// kernels that use them are in pmp_binned.hip.
+#include "pmp_internal.h"
+
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+namespace pmp {
+
+namespace {
+
+// Count-based blocking: a multiple of 256 blocks (one or more per CU) of at
+// most kBinMaxBlock rows each.
+void split_by_count(int count, int &blocks, int &size)
+{
+    const long long per = 256LL * kBinMaxBlock;
+    const long long k = std::max<long long>(1, (count + per - 1) / per);
+    blocks = (int)(256 * k);
+    size = (int)std::max<long long>(1, (count + blocks - 1) / blocks);
+    blocks = (int)std::max<long long>(1, (count + size - 1) / size);
+}
+
+// Row cap of a balanced block: a quarter above the count-based size, within
+// kBinMaxBlock.
+int row_cap(int size) { return std::min(kBinMaxBlock, size + (size + 3) / 4); }
+
+// Close a block once it holds `quota` nonzeros or `cap` rows.  Blocks closed
+// by the quota number at most nnz / quota, blocks closed by the cap at most
+// count / cap, so there are at most blocks0 + count / cap + 1 of them.
+int cut_blocks(const int *ptr, int count, long long nnz, int blocks0, int cap, int *starts,
+               int &most)
+{
+    const long long quota = std::max<long long>(1, (nnz + blocks0 - 1) / blocks0);
+    int nb = 0, s = 0;
+    most = 0;
+    starts[0] = 0;
+    for (int i = 1; i <= count; ++i)
+        if (i == count || i - s >= cap || (long long)ptr[i] - ptr[s] >= quota) {
+            starts[++nb] = i;
+            most = std::max(most, i - s);
+            s = i;
+        }
+    return nb;
+}
+
+}  // namespace
+
+BinnedPlan binned_plan(int m, int n)
+{
+    BinnedPlan bp{};
+    int p0, lb0, q0, sb0;
+    split_by_count(m, p0, lb0);
+    split_by_count(n, q0, sb0);
+    bp.LB = row_cap(lb0);
+    bp.P = p0 + (m + bp.LB - 1) / bp.LB + 1;
+    bp.SB = sb0;
+    bp.Q = q0;
+    return bp;
+}
+
+void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &bp, int *lbs,
+                   int *sbs)
+{
+    int p0, lb0, q0, sb0;
+    split_by_count(m, p0, lb0);
+    split_by_count(n, q0, sb0);
+    // links: balanced by nonzeros (a congested link has thousands)
+    bp.P = cut_blocks(row_ptr, m, nnz, p0, row_cap(lb0), lbs, bp.LB);
+    // streams: by count (routes are short), so the block of stream j is j / SB
+    bp.Q = q0;
+    bp.SB = sb0;
+    for (int q = 0; q <= q0; ++q) sbs[q] = (int)std::min<long long>((long long)q * sb0, n);
+}
+
+void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
+                       const int *lbs, const int *sbs, int *ox, int *ov, uint16_t *lix,
+                       uint16_t *six)
+{
+    const long long P = bp.P, Q = bp.Q;
+    (void)m;
+    (void)n;
+    // Link block p touches only tiles (p, *) and their slots, so the counting
+    // and the placing passes split over link blocks across host threads.
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto over_blocks = [&](auto &&body) {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&, t] {
+                for (long long p = t; p < P; p += nth) body(p);
+            });
+        for (auto &th : pool) th.join();
+    };
+    std::vector<int> cnt((size_t)(P * Q), 0);
+    over_blocks([&](long long p) {
+        int *c = cnt.data() + p * Q;
+        for (int l = lbs[p]; l < lbs[p + 1]; ++l)
+            for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) c[col_idx[k] / bp.SB]++;
+    });
+    long long acc = 0;   // < nnz < 2^31
+    for (long long p = 0; p < P; ++p)
+        for (long long q = 0; q < Q; ++q) {
+            ox[p * Q + q] = (int)acc;
+            acc += cnt[(size_t)(p * Q + q)];
+        }
+    ox[P * Q] = (int)acc;
+    acc = 0;
+    for (long long q = 0; q < Q; ++q)
+        for (long long p = 0; p < P; ++p) {
+            ov[q * P + p] = (int)acc;
+            acc += cnt[(size_t)(p * Q + q)];
+        }
+    ov[Q * P] = (int)acc;
+    over_blocks([&](long long p) {
+        int *c = cnt.data() + p * Q;
+        std::fill(c, c + Q, 0);
+        for (int l = lbs[p]; l < lbs[p + 1]; ++l)
+            for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) {
+                const int j = col_idx[k];
+                const long long q = j / bp.SB;
+                const int r = c[q]++;   // rank in the tile, CSR order
+                lix[ox[p * Q + q] + r] = (uint16_t)(l - lbs[p]);
+                six[ov[q * P + p] + r] = (uint16_t)(j - sbs[q]);
+            }
+    });
+}
+
+}  // namespace pmp
