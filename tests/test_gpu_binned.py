@@ -97,3 +97,15 @@ def test_binned_adjoint_matches_gather_adjoint():
     assert abs(Jb - Jg) <= 1e-12 * abs(Jg)
     assert rel(gcb, gcg) <= 1e-12 and rel(gwb, gwg) <= 1e-12
     assert rel(xb, xg) <= 1e-12
+
+
+def test_auto_layout_threshold():
+    # FP32 from 2^21 nonzeros (with m, n >= 256): binned; below, or FP64: gather
+    big = I.medium(scale=0.5).rounded(np.float32)          # about 2.5e6 nonzeros
+    small = I.medium(scale=0.2).rounded(np.float32)        # about 1e6
+    assert big.nnz >= 1 << 21 > small.nnz
+    for inst, dtype, want in ((big, torch.float32, "binned"), (small, torch.float32, "gather"),
+                              (big, torch.float64, "gather")):
+        s = Solver(inst, dtype=dtype)
+        assert s.layout_in_use() == want
+        s.close()
