@@ -17,8 +17,10 @@
 // dP/dS = rho x^2 / (rho L x^2 + w) and dP/dw = x / (rho L x^2 + w) follow
 // from the recorded rate alone; the linear prox has dP/dS = 1/L and
 // dP/dw = 1/(rho L).  The link gather of iteration t is fused with the link
-// step of iteration t - 1.
-#include "pmp_internal.h"
+// step of iteration t - 1.  The per-stream and per-link steps
+// (adj_stream_step, adj_link_step) are in pmp_device.h, shared with the
+// binned layout's reverse kernels in pmp_binned.hip.
+#include "pmp_device.h"
 
 #include <cmath>
 
@@ -59,53 +61,6 @@ __device__ __forceinline__ void gather_stage_d(const int *__restrict__ idx,
     }
 }
 
-__device__ __forceinline__ void link_step(const AdjDev &a, int l, int deg, double alpha,
-                                          uint8_t mu)
-{
-    const double B = a.B[l], Z = a.Z[l], U = a.U[l];
-    const double inv = 1.0 / ((double)deg + 1.0);
-    const double pbb = alpha * (U - B - Z);
-    const double psb = alpha * Z + pbb * inv;
-    const double m1 = mu ? 1.0 : 0.0;
-    a.ybar[l] = pbb * inv;
-    a.cbar[l] -= (1.0 - m1) * psb;
-    a.B[l] = (1.0 - alpha) * B;
-    a.Z[l] = (1.0 - alpha) * Z + m1 * psb;
-    a.U[l] = U - m1 * psb;
-}
-
-template <typename T>
-__device__ __forceinline__ void stream_step(const Dev<T> &d, const AdjDev &a, const T *xt,
-                                            int j, int L, double ysum, int last, double rho)
-{
-    double xbar = d.alpha * a.A[j] + ysum;
-    if (last) xbar += a.ext[j];
-    const double x = (double)xt[j];
-    const double wsig = (double)d.wsig[j];
-    double sbar = 0.0;
-    if (L > 0 && x > d.lo && x < d.hi) {
-        double dS, dw;
-        if (d.util && d.util[j] == PMP_UTIL_ALPHA2) {
-            // rho L x^3 - rho S x^2 - w = 0:  dx/dS = rho x^3 / (rho L x^3 + 2w),
-            // dx/dw = x / (rho L x^3 + 2w)
-            const double den = rho * (double)L * x * x * x + 2.0 * wsig;
-            dS = rho * x * x * x / den;
-            dw = x / den;
-        } else if (wsig > 0.0) {
-            const double den = rho * (double)L * x * x + wsig;
-            dS = rho * x * x / den;
-            dw = x / den;
-        } else {
-            dS = 1.0 / (double)L;
-            dw = 1.0 / (rho * (double)L);
-        }
-        sbar = xbar * dS;
-        a.wbar[j] += xbar * dw;
-    }
-    a.A[j] = (1.0 - d.alpha) * a.A[j] + (double)L * sbar;
-    a.Sbar[j] = sbar;
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const T *xt, int last)
 {
@@ -124,14 +79,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const
             const int b = d.col_ptr[j] - e0, e = d.col_ptr[j + 1] - e0;
             double acc = 0.0;
             for (int k = b; k < e; ++k) acc += sy[k];
-            stream_step<T>(d, a, xt, j, e - b, acc, last, rho);
+            adj_stream_step<T>(d, a, xt, j, e - b, acc, last, rho);
         }
     } else {
         double acc = 0.0;
         for (int k = threadIdx.x; k < cnt; k += kBlock)
             acc += a.ybar[__builtin_nontemporal_load(d.row_idx + e0 + k)];
         acc = block_sum_d(acc, sred);
-        if (threadIdx.x == 0) stream_step<T>(d, a, xt, s0, cnt, acc, last, rho);
+        if (threadIdx.x == 0) adj_stream_step<T>(d, a, xt, s0, cnt, acc, last, rho);
     }
 }
 
@@ -167,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_link(Dev<T> d, AdjDev a, const u
     if (l >= 0) {
         a.B[l] += acc;
         a.U[l] -= acc;
-        if (mu_prev) link_step(a, l, deg, d.alpha, mu_prev[l]);
+        if (mu_prev) adj_link_step(a, l, deg, d.alpha, mu_prev[l]);
     }
 }
 
@@ -175,7 +130,7 @@ template <typename T>
 __global__ void k_adj_link_only(Dev<T> d, AdjDev a, const uint8_t *mu)
 {
     for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += gridDim.x * blockDim.x)
-        link_step(a, l, d.row_ptr[l + 1] - d.row_ptr[l], d.alpha, mu[l]);
+        adj_link_step(a, l, d.row_ptr[l + 1] - d.row_ptr[l], d.alpha, mu[l]);
 }
 
 template <typename T>

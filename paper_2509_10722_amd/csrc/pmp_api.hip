@@ -584,11 +584,13 @@ namespace {
 
 struct AdjLayout {
     size_t ckpt, final_state, xK, tape_x, tape_mu, A, Sbar, wbar, ext, B, Z, U, ybar, cbar;
+    size_t my, ms;   // binned layout: FP64 messages of ybar and Sbar
     size_t part, J, total, state;
     int nck, nobj;
 };
 
-AdjLayout adj_plan(int m, int n, int K, int s, size_t sz)
+// msgs: message slots of the binned layout (0 for the gather layout)
+AdjLayout adj_plan(int m, int n, long long msgs, int K, int s, size_t sz)
 {
     AdjLayout L{};
     size_t off = 0;
@@ -616,8 +618,18 @@ AdjLayout adj_plan(int m, int n, int K, int s, size_t sz)
     L.cbar = take((size_t)m * 8);
     L.part = take((size_t)L.nobj * 8);
     L.J = take(8);
+    if (msgs > 0) {
+        L.my = take((size_t)msgs * 8);
+        L.ms = take((size_t)msgs * 8);
+    }
     L.total = off;
     return L;
+}
+
+AdjLayout adj_plan_for(const pmp_handle *h, int K, int s)
+{
+    const int binned = h->dtype == PMP_F32 ? h->df.binned : h->dd.binned;
+    return adj_plan(h->m, h->n, binned ? h->nnz : 0, K, s, h->dtype == PMP_F64 ? 8 : 4);
 }
 
 template <typename T>
@@ -658,7 +670,7 @@ template <typename T>
 pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
 {
     Dev<T> &d = dev_of<T>(h);
-    const AdjLayout L = adj_plan(h->m, h->n, K, s, sizeof(T));
+    const AdjLayout L = adj_plan_for(h, K, s);
     hipStream_t st = h->stream;
     pmp_status rc;
     launch_ctl_clear_done(h->ctl, st);
@@ -695,16 +707,18 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
     Dev<T> &d = dev_of<T>(h);
     const int K = h->adj_K, s = h->adj_s;
     char *ws = h->adj_ws;
-    const AdjLayout L = adj_plan(h->m, h->n, K, s, sizeof(T));
+    const AdjLayout L = adj_plan_for(h, K, s);
     const AdjDev a = adj_views(ws, L);
     hipStream_t st = h->stream;
     pmp_status rc;
     T *tape_x = (T *)(ws + L.tape_x);
     uint8_t *tape_mu = (uint8_t *)(ws + L.tape_mu);
+    double *my = (double *)(ws + L.my), *ms = (double *)(ws + L.ms);
     launch_ctl_clear_done(h->ctl, st);
     // adjoint seeds from x^K
     if (h->n) HIP_TRY(hipMemcpyAsync(d.x, ws + L.xK, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
     launch_adj_init<T>(d, a, st);
+    if (d.binned) launch_bin_adj_emit<T>(d, a, my, st);   // ybar = 0
     for (int seg = L.nck - 1; seg >= 0; --seg) {
         const int t0 = seg * s, t1 = std::min(t0 + s, K);
         if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)seg * L.state, false)) != PMP_OK) return rc;
@@ -717,12 +731,20 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
             launch_slack_mask<T>(d, tape_mu + (size_t)(t - t0 - 1) * h->m, st);
             link_pass<T>(d, kPlain, 0, 0, st);
         }
-        if (t1 < K)   // link step of iteration t1, deferred from the later segment
+        if (t1 < K) {   // link step of iteration t1, deferred from the later segment
             launch_adj_link_only<T>(d, a, tape_mu + (size_t)(t1 - t0 - 1) * h->m, st);
+            if (d.binned) launch_bin_adj_emit<T>(d, a, my, st);
+        }
         for (int t = t1; t > t0; --t) {
-            launch_adj_stream<T>(d, a, tape_x + (size_t)(t - t0 - 1) * h->n, t == K, st);
+            const T *xt = tape_x + (size_t)(t - t0 - 1) * h->n;
             const uint8_t *mu_prev = t - 1 > t0 ? tape_mu + (size_t)(t - 2 - t0) * h->m : nullptr;
-            launch_adj_link<T>(d, a, mu_prev, st);
+            if (d.binned) {
+                launch_bin_adj_stream<T>(d, a, xt, t == K, my, ms, st);
+                launch_bin_adj_link<T>(d, a, mu_prev, ms, my, st);
+            } else {
+                launch_adj_stream<T>(d, a, xt, t == K, st);
+                launch_adj_link<T>(d, a, mu_prev, st);
+            }
         }
     }
     launch_adj_out<T>(d, a, gc, gw, st);
@@ -741,7 +763,7 @@ extern "C" {
 pmp_status pmp_adjoint_workspace_size(pmp_handle *h, int32_t K, int32_t s, size_t *bytes)
 {
     if (!h || !bytes || K < 1 || s < 1) return fail(PMP_ERR_INVALID, "bad argument");
-    *bytes = adj_plan(h->m, h->n, K, s, h->dtype == PMP_F64 ? 8 : 4).total;
+    *bytes = adj_plan_for(h, K, s).total;
     return PMP_OK;
 }
 
@@ -749,7 +771,7 @@ pmp_status pmp_forward_ckpt(pmp_handle *h, int32_t K, int32_t s, void *adj_works
                             size_t adj_bytes, double *J)
 {
     if (!h || K < 1 || s < 1) return fail(PMP_ERR_INVALID, "bad argument");
-    const size_t need = adj_plan(h->m, h->n, K, s, h->dtype == PMP_F64 ? 8 : 4).total;
+    const size_t need = adj_plan_for(h, K, s).total;
     if (!adj_workspace || adj_bytes < need)
         return fail(PMP_ERR_SHAPE, "adjoint workspace of %zu bytes needed, %zu given", need, adj_bytes);
     if ((uintptr_t)adj_workspace % kAlign) return fail(PMP_ERR_INVALID, "adjoint workspace must be 256-byte aligned");

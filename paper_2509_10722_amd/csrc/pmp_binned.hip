@@ -360,6 +360,77 @@ PMP_BIN_KERNEL void k_bin_emit(Dev<T> d, int apply)
     emit_tiles<T>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, d.mv);
 }
 
+// Reverse mode in the binned layout: the two sums of a reversed iteration,
+// R^T ybar (per stream) and R Sbar (per link), move as FP64 messages through
+// the same tiles as the forward messages (ybar in the v layout, Sbar in the x
+// layout).  FP64 messages give up the order independence of the FP32 ones,
+// so these sums match the gather layout's to rounding only.
+template <typename T>
+PMP_BIN_KERNEL void k_bin_adj_stream(Dev<T> d, AdjDev a, const T *xt, int last,
+                                     const double *my, double *ms)
+{
+    extern __shared__ acc_t S[];
+    const int q = xcd_block(blockIdx.x, gridDim.x);
+    const int j0 = d.sbs[q];
+    const int ns = d.sbs[q + 1] - j0;
+    for (int i = threadIdx.x; i < ns; i += kBinThreads) S[i] = 0.0;
+    __syncthreads();
+    accumulate<double, false>(my, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
+    __syncthreads();
+    const double rho = d.ctl->rho;
+    for (int i = threadIdx.x; i < ns; i += kBinThreads) {
+        const int j = j0 + i;
+        const int L = d.rlen ? (int)d.rlen[j] : d.col_ptr[j + 1] - d.col_ptr[j];
+        adj_stream_step<T>(d, a, xt, j, L, (double)S[i], last, rho);
+        S[i] = a.Sbar[j];
+    }
+    __syncthreads();
+    emit_tiles<double>(d.ov + (long long)q * d.P, d.ox + q, d.Q, d.P, d.six, S, ms);
+}
+
+// R Sbar per link, then (mu_prev given) the link step of the iteration
+// before, whose ybar goes out as messages for the next stream step.
+template <typename T>
+PMP_BIN_KERNEL void k_bin_adj_link(Dev<T> d, AdjDev a, const uint8_t *mu_prev, const double *ms,
+                                   double *my)
+{
+    extern __shared__ acc_t Y[];
+    const int p = xcd_block(blockIdx.x, gridDim.x);
+    const int l0 = d.lbs[p];
+    const int nl = d.lbs[p + 1] - l0;
+    for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = 0.0;
+    __syncthreads();
+    accumulate<double, false>(ms, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nl; i += kBinThreads) {
+        const int l = l0 + i;
+        const double vbar = (double)Y[i];
+        a.B[l] += vbar;
+        a.U[l] -= vbar;
+        if (mu_prev) {
+            const int deg = d.dlen ? (int)d.dlen[l] : d.row_ptr[l + 1] - d.row_ptr[l];
+            adj_link_step(a, l, deg, d.alpha, mu_prev[l]);
+            Y[i] = a.ybar[l];
+        }
+    }
+    if (!mu_prev) return;   // ybar unchanged: its messages still hold
+    __syncthreads();
+    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, my);
+}
+
+// ybar messages from a.ybar (after it changed outside k_bin_adj_link).
+template <typename T>
+PMP_BIN_KERNEL void k_bin_adj_emit(Dev<T> d, AdjDev a, double *my)
+{
+    extern __shared__ acc_t Y[];
+    const int p = xcd_block(blockIdx.x, gridDim.x);
+    const int l0 = d.lbs[p];
+    const int nl = d.lbs[p + 1] - l0;
+    for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = a.ybar[l0 + i];
+    __syncthreads();
+    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ov + p, d.P, d.Q, d.lix, Y, my);
+}
+
 }  // namespace
 
 void binned_configure()
@@ -380,6 +451,12 @@ void binned_configure()
     PMP_BIN_ATTR((k_bin_link<double, kCheck>));
     PMP_BIN_ATTR((k_bin_emit<float>));
     PMP_BIN_ATTR((k_bin_emit<double>));
+    PMP_BIN_ATTR((k_bin_adj_stream<float>));
+    PMP_BIN_ATTR((k_bin_adj_stream<double>));
+    PMP_BIN_ATTR((k_bin_adj_link<float>));
+    PMP_BIN_ATTR((k_bin_adj_link<double>));
+    PMP_BIN_ATTR((k_bin_adj_emit<float>));
+    PMP_BIN_ATTR((k_bin_adj_emit<double>));
 #undef PMP_BIN_ATTR
 }
 
@@ -424,11 +501,44 @@ void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s)
                        s, d, apply);
 }
 
+template <typename T>
+void launch_bin_adj_stream(const Dev<T> &d, const AdjDev &a, const T *xt, int last,
+                           const double *my, double *ms, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_bin_adj_stream<T>), dim3(d.Q), dim3(kBinThreads),
+                       ((size_t)d.SB) * sizeof(acc_t), s, d, a, xt, last, my, ms);
+}
+
+template <typename T>
+void launch_bin_adj_link(const Dev<T> &d, const AdjDev &a, const uint8_t *mu_prev,
+                         const double *ms, double *my, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_bin_adj_link<T>), dim3(d.P), dim3(kBinThreads),
+                       ((size_t)d.LB) * sizeof(acc_t), s, d, a, mu_prev, ms, my);
+}
+
+template <typename T>
+void launch_bin_adj_emit(const Dev<T> &d, const AdjDev &a, double *my, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_bin_adj_emit<T>), dim3(d.P), dim3(kBinThreads),
+                       ((size_t)d.LB) * sizeof(acc_t), s, d, a, my);
+}
+
 template void launch_bin_stream<float>(const Dev<float> &, int, hipStream_t);
 template void launch_bin_stream<double>(const Dev<double> &, int, hipStream_t);
 template void launch_bin_link<float>(const Dev<float> &, int, hipStream_t);
 template void launch_bin_link<double>(const Dev<double> &, int, hipStream_t);
 template void launch_bin_emit<float>(const Dev<float> &, int, hipStream_t);
 template void launch_bin_emit<double>(const Dev<double> &, int, hipStream_t);
+template void launch_bin_adj_stream<float>(const Dev<float> &, const AdjDev &, const float *, int,
+                                           const double *, double *, hipStream_t);
+template void launch_bin_adj_stream<double>(const Dev<double> &, const AdjDev &, const double *,
+                                            int, const double *, double *, hipStream_t);
+template void launch_bin_adj_link<float>(const Dev<float> &, const AdjDev &, const uint8_t *,
+                                         const double *, double *, hipStream_t);
+template void launch_bin_adj_link<double>(const Dev<double> &, const AdjDev &, const uint8_t *,
+                                          const double *, double *, hipStream_t);
+template void launch_bin_adj_emit<float>(const Dev<float> &, const AdjDev &, double *, hipStream_t);
+template void launch_bin_adj_emit<double>(const Dev<double> &, const AdjDev &, double *, hipStream_t);
 
 }  // namespace pmp

@@ -178,6 +178,55 @@ __device__ __forceinline__ double link_update(const Dev<T> &d, int l, int deg, d
     return link_update_in<T, MODE, WRITE_V>(d, l, deg, y, link_load<T, MODE>(d, l), r2, s2);
 }
 
+// ---- reverse mode (one reversed iteration; see pmp_adjoint.hip) ------------
+
+__device__ __forceinline__ void adj_link_step(const AdjDev &a, int l, int deg, double alpha,
+                                          uint8_t mu)
+{
+    const double B = a.B[l], Z = a.Z[l], U = a.U[l];
+    const double inv = 1.0 / ((double)deg + 1.0);
+    const double pbb = alpha * (U - B - Z);
+    const double psb = alpha * Z + pbb * inv;
+    const double m1 = mu ? 1.0 : 0.0;
+    a.ybar[l] = pbb * inv;
+    a.cbar[l] -= (1.0 - m1) * psb;
+    a.B[l] = (1.0 - alpha) * B;
+    a.Z[l] = (1.0 - alpha) * Z + m1 * psb;
+    a.U[l] = U - m1 * psb;
+}
+
+template <typename T>
+__device__ __forceinline__ void adj_stream_step(const Dev<T> &d, const AdjDev &a, const T *xt,
+                                            int j, int L, double ysum, int last, double rho)
+{
+    double xbar = d.alpha * a.A[j] + ysum;
+    if (last) xbar += a.ext[j];
+    const double x = (double)xt[j];
+    const double wsig = (double)d.wsig[j];
+    double sbar = 0.0;
+    if (L > 0 && x > d.lo && x < d.hi) {
+        double dS, dw;
+        if (d.util && d.util[j] == PMP_UTIL_ALPHA2) {
+            // rho L x^3 - rho S x^2 - w = 0:  dx/dS = rho x^3 / (rho L x^3 + 2w),
+            // dx/dw = x / (rho L x^3 + 2w)
+            const double den = rho * (double)L * x * x * x + 2.0 * wsig;
+            dS = rho * x * x * x / den;
+            dw = x / den;
+        } else if (wsig > 0.0) {
+            const double den = rho * (double)L * x * x + wsig;
+            dS = rho * x * x / den;
+            dw = x / den;
+        } else {
+            dS = 1.0 / (double)L;
+            dw = 1.0 / (rho * (double)L);
+        }
+        sbar = xbar * dS;
+        a.wbar[j] += xbar * dw;
+    }
+    a.A[j] = (1.0 - d.alpha) * a.A[j] + (double)L * sbar;
+    a.Sbar[j] = sbar;
+}
+
 // ---- residual reduction, stop rule and rho balancing ---------------------
 
 // Thread 0 of the check-finalize kernel: residual norms (Section III-F), the

@@ -191,6 +191,16 @@ void launch_bin_link(const Dev<T> &d, int mode, hipStream_t s);
 template <typename T>
 void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s);
 void binned_configure();
+// Reverse mode in the binned layout: my holds ybar in the v-message layout,
+// ms holds Sbar in the x-message layout (FP64, one per nonzero each).
+template <typename T>
+void launch_bin_adj_stream(const Dev<T> &d, const AdjDev &a, const T *xt, int last,
+                           const double *my, double *ms, hipStream_t s);
+template <typename T>
+void launch_bin_adj_link(const Dev<T> &d, const AdjDev &a, const uint8_t *mu_prev,
+                         const double *ms, double *my, hipStream_t s);
+template <typename T>
+void launch_bin_adj_emit(const Dev<T> &d, const AdjDev &a, double *my, hipStream_t s);
 
 // Batched solve (pmp_batch.hip): many instances concatenated block-diagonally
 // into one global pattern, iterated together by one persistent kernel with

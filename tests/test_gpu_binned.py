@@ -109,3 +109,21 @@ def test_auto_layout_threshold():
         s = Solver(inst, dtype=dtype)
         assert s.layout_in_use() == want
         s.close()
+
+
+def test_binned_adjoint_fp32_matches_gather_adjoint():
+    # FP32 forward passes agree bitwise between the layouts; the reverse sums
+    # run in FP64 in both, in a different order
+    inst = I.adjoint(scale=0.05).rounded(np.float32)
+    out = []
+    for layout in (PMP_LAYOUT_BINNED, PMP_LAYOUT_GATHER):
+        s = Solver(inst, dtype=torch.float32, layout=layout, adapt_every=0)
+        s.iterate(11)
+        J = s.forward_ckpt(60, 7)
+        gc, gw = s.backward()
+        out.append((J, host(gc), host(gw)))
+        s.close()
+    (Jb, gcb, gwb), (Jg, gcg, gwg) = out
+    print(f"fp32 adjoint: J {abs(Jb - Jg) / abs(Jg):.1e} c {rel(gcb, gcg):.1e} w {rel(gwb, gwg):.1e}")
+    assert Jb == Jg
+    assert rel(gcb, gcg) <= 1e-6 and rel(gwb, gwg) <= 1e-6
