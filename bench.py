@@ -500,6 +500,9 @@ def main():
         "setup_s": round(setup_s, 3),
     }
     line.update(out_tol)
+    if cpu and out_tol.get("tol_converged"):
+        # the oracle runs the same iteration, so it needs about the same count
+        cpu["time_to_tol_s_extrapolated"] = round(out_tol["iters_to_tol"] / cpu["value"], 1)
     print(json.dumps(line), flush=True)
 
 
