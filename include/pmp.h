@@ -95,7 +95,7 @@ typedef struct {
 
 /* Solver controls (Section III-F, III-G).
  *   rho0         initial penalty (> 0)
- *   alpha        over-relaxation in [1, 2) (the paper uses 1.6)
+ *   alpha        over-relaxation in (0, 2) (the paper uses 1.6)
  *   mu, gamma    residual-balancing thresholds (> 1; the paper uses 2, 1.1)
  *   eps_abs      absolute tolerance; stop when ||r||, ||s|| < eps_abs sqrt(J),
  *                J = nnz + m terminals
@@ -105,11 +105,14 @@ typedef struct {
  *   max_iter     iteration cap of one pmp_solve call
  *   layout       sparse layout of the iteration: PMP_LAYOUT_AUTO picks
  *                PMP_LAYOUT_BINNED for FP32 problems with nnz >= 2^21 and
- *                m, n >= 256, PMP_LAYOUT_GATHER otherwise.  GATHER: CSR / CSC passes with
- *                LDS-staged gathers.  BINNED: R tiled into link-block x
- *                stream-block tiles with one FP32 message per nonzero per
- *                direction, streamed through HBM in coalesced runs (for
- *                large unstructured R, where random gathers are slow). */
+ *                m, n >= 256, PMP_LAYOUT_GATHER otherwise.  GATHER: CSR /
+ *                CSC passes with LDS-staged gathers (fastest while the
+ *                gathered vectors stay in cache).  BINNED: R tiled into
+ *                link-block x stream-block tiles with one message per
+ *                nonzero per direction, streamed through HBM in coalesced
+ *                runs (for large unstructured R, where random gathers are
+ *                slow); with FP32 its sums equal the gather layout's bit for
+ *                bit whenever they are exact in FP64. */
 typedef enum { PMP_LAYOUT_AUTO = 0, PMP_LAYOUT_GATHER = 1, PMP_LAYOUT_BINNED = 2 } pmp_layout;
 typedef struct {
     double rho0, alpha, mu, gamma, eps_abs;
@@ -213,8 +216,11 @@ pmp_status pmp_prune(pmp_handle *h, const uint8_t *failed, void *workspace,
  * stream. */
 pmp_status pmp_get_path_prices(pmp_handle *h, void *pi);
 
-/* Device pointers to the internal rate and price-related vectors (x[n] and
- * u[m]) for zero-copy inspection; valid until pmp_destroy. */
+/* Device pointers to the internal vectors for zero-copy inspection, in the
+ * problem's dtype: x[n] rates, u[m] scaled duals (prices / rho), and the
+ * compact iterate a[n], b[m], zs[m], v[m] = b - u.  Valid until pmp_destroy
+ * and current whenever the handle's stream has finished the work of the
+ * calls made so far (any pointer may be NULL). */
 pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **b,
                             void **zs, void **v);
 

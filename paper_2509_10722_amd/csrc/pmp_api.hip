@@ -686,6 +686,7 @@ pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
         link_pass<T>(d, kPlain, 0, 0, st);
     }
     h->iter_enq += K;
+    launch_refresh_v<T>(d, st);   // v = b - u (the binned passes keep it in messages)
     if ((rc = copy_state<T>(h, ws + L.final_state, true)) != PMP_OK) return rc;
     if (h->n) HIP_TRY(hipMemcpyAsync(ws + L.xK, d.x, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
     launch_objective<T>(d, (double *)(ws + L.part), L.nobj, (double *)(ws + L.J), st);
