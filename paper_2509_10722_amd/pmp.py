@@ -8,7 +8,6 @@ them for one instance.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 import numpy as np
