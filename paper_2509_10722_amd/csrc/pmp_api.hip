@@ -76,7 +76,7 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
     L.nlb_max = (int)std::min<long long>((long long)m, m / kBlock + 2 * nnz / kCap + 2);
     L.binned = use_binned(m, n, nnz, sz, layout);
     if (L.binned) {
-        L.bp = binned_plan(m, n);   // bounds; the blocks are cut at setup
+        L.bp = binned_plan(m, n, nnz);   // bounds; the blocks are cut at setup
         L.nsb_max = std::max(L.nsb_max, L.bp.Q);
         L.nlb_max = std::max(L.nlb_max, L.bp.P);
     }

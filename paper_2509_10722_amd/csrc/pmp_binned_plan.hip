@@ -11,15 +11,28 @@ namespace pmp {
 
 namespace {
 
-// Count-based blocking: a multiple of 256 blocks (one or more per CU) of at
-// most kBinMaxBlock rows each.
-void split_by_count(int count, int &blocks, int &size)
+// Count-based blocking: a multiple of 256 blocks (at least `groups` x 256,
+// one or more per CU) of at most kBinMaxBlock rows each.
+void split_by_count(int count, int groups, int &blocks, int &size)
 {
     const long long per = 256LL * kBinMaxBlock;
-    const long long k = std::max<long long>(1, (count + per - 1) / per);
+    const long long k = std::max<long long>(groups, (count + per - 1) / per);
     blocks = (int)(256 * k);
     size = (int)std::max<long long>(1, (count + blocks - 1) / blocks);
     blocks = (int)std::max<long long>(1, (count + size - 1) / size);
+}
+
+// Blocks of both sides.  A side with fewer than 512 blocks (one workgroup
+// per CU) gets twice as many when the tiles keep at least 64 nonzeros on
+// average, so that two workgroups share each CU: measured on MI355X, +9% to
+// +13% at 2.5e7 to 6e7 nonzeros, while at 5e6 nonzeros the smaller tiles
+// cost more than the second workgroup gains.
+void count_blocks(int m, int n, long long nnz, int &p0, int &lb0, int &q0, int &sb0)
+{
+    split_by_count(m, 1, p0, lb0);
+    split_by_count(n, 1, q0, sb0);
+    if (p0 < 512 && m >= 512 && nnz >= 64LL * 2 * p0 * q0) split_by_count(m, 2, p0, lb0);
+    if (q0 < 512 && n >= 512 && nnz >= 64LL * p0 * 2 * q0) split_by_count(n, 2, q0, sb0);
 }
 
 // Row cap of a balanced block: a quarter above the count-based size, within
@@ -47,12 +60,11 @@ int cut_blocks(const int *ptr, int count, long long nnz, int blocks0, int cap, i
 
 }  // namespace
 
-BinnedPlan binned_plan(int m, int n)
+BinnedPlan binned_plan(int m, int n, long long nnz)
 {
     BinnedPlan bp{};
     int p0, lb0, q0, sb0;
-    split_by_count(m, p0, lb0);
-    split_by_count(n, q0, sb0);
+    count_blocks(m, n, nnz, p0, lb0, q0, sb0);
     bp.LB = row_cap(lb0);
     bp.P = p0 + (m + bp.LB - 1) / bp.LB + 1;
     bp.SB = sb0;
@@ -64,8 +76,7 @@ void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &
                    int *sbs)
 {
     int p0, lb0, q0, sb0;
-    split_by_count(m, p0, lb0);
-    split_by_count(n, q0, sb0);
+    count_blocks(m, n, nnz, p0, lb0, q0, sb0);
     // links: balanced by nonzeros (a congested link has thousands)
     bp.P = cut_blocks(row_ptr, m, nnz, p0, row_cap(lb0), lbs, bp.LB);
     // streams: by count (routes are short), so the block of stream j is j / SB

@@ -171,7 +171,7 @@ struct BinnedPlan {
     int LB, SB;   // most links / streams in one block (LDS sums per workgroup)
 };
 // Bounds of the plan from the sizes alone (workspace sizing).
-BinnedPlan binned_plan(int m, int n);
+BinnedPlan binned_plan(int m, int n, long long nnz);
 // Block boundaries lbs[P+1] of the links, balanced by nonzeros (a block
 // closes once it holds the nonzero quota or its row cap), and sbs[Q+1] of
 // the streams, by count (stream j is in block j / SB); sets P, Q, LB, SB of
