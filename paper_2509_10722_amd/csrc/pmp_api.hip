@@ -44,7 +44,7 @@ constexpr int kSlots = 4;   // pipelined chunks in flight in pmp_solve
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t mx, mv, lix, six, ox, ov, lbs, sbs, rlen, dlen;
+    size_t mx, mv, lix, six, ox, ov, oxq, ovp, lbs, sbs, rlen, dlen;
     bool binned;
     BinnedPlan bp;
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
@@ -119,6 +119,8 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
         L.six = take((size_t)(nnz + 4) * 2);
         L.ox = take(tiles * 4);
         L.ov = take(tiles * 4);
+        L.oxq = take(tiles * 4);
+        L.ovp = take(tiles * 4);
         L.lbs = take(((size_t)L.bp.P + 1) * 4);
         L.sbs = take(((size_t)L.bp.Q + 1) * 4);
         L.rlen = take((size_t)n);
@@ -407,6 +409,8 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         d.six = (const uint16_t *)(ws + L.six);
         d.ox = (const int *)(ws + L.ox);
         d.ov = (const int *)(ws + L.ov);
+        d.oxq = (const int *)(ws + L.oxq);
+        d.ovp = (const int *)(ws + L.ovp);
         const size_t tiles = (size_t)d.P * (size_t)d.Q + 1;
         std::vector<int> hcolidx((size_t)nnz);
         if (nnz) HIP_TRY(hipMemcpyAsync(hcolidx.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
@@ -417,8 +421,17 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
                           ov.data(), lix.data(), six.data());
         HIP_TRY(hipMemcpyAsync((void *)d.lbs, lbs.data(), ((size_t)d.P + 1) * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void *)d.sbs, sbs.data(), ((size_t)d.Q + 1) * 4, hipMemcpyHostToDevice, s));
+        // each emission walks its destination offsets in its own block order
+        std::vector<int> oxq(tiles - 1), ovp(tiles - 1);
+        for (long long p = 0; p < d.P; ++p)
+            for (long long q = 0; q < d.Q; ++q) {
+                oxq[(size_t)(q * d.P + p)] = ox[(size_t)(p * d.Q + q)];
+                ovp[(size_t)(p * d.Q + q)] = ov[(size_t)(q * d.P + p)];
+            }
         HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.oxq, oxq.data(), (tiles - 1) * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void *)d.ovp, ovp.data(), (tiles - 1) * 4, hipMemcpyHostToDevice, s));
         if (nnz) {
             HIP_TRY(hipMemcpyAsync((void *)d.lix, lix.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
             HIP_TRY(hipMemcpyAsync((void *)d.six, six.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));

@@ -107,6 +107,8 @@ struct Dev {
     const uint16_t *six;            // [nnz] local stream of each mv entry
     const int *ox;                  // [P Q + 1] tile offsets in mx, p-major
     const int *ov;                  // [Q P + 1] tile offsets in mv, q-major
+    const int *oxq;                 // [Q P] the offsets of ox listed q-major
+    const int *ovp;                 // [P Q] the offsets of ov listed p-major
 };
 
 // Adjoint (reverse-mode) vectors, all FP64, in the adjoint workspace.
