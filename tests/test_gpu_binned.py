@@ -127,3 +127,57 @@ def test_binned_adjoint_fp32_matches_gather_adjoint():
     print(f"fp32 adjoint: J {abs(Jb - Jg) / abs(Jg):.1e} c {rel(gcb, gcg):.1e} w {rel(gwb, gwg):.1e}")
     assert Jb == Jg
     assert rel(gcb, gcg) <= 1e-6 and rel(gwb, gwg) <= 1e-6
+
+
+def _ragged_instance(seed=3):
+    """Streams with empty routes (a whole range of them), links that carry no
+    stream, one route of 300 links and one link on 5000 streams: the cases
+    where a binned tile or block is empty and where the 8-bit length tables
+    give way to the CSR/CSC lengths."""
+    rng = np.random.default_rng(seed)
+    m, n = 3001, 20011
+    dead_links = np.arange(100, 200)
+    live = np.setdiff1d(np.arange(m), dead_links)
+    routes = []
+    for j in range(n):
+        if 5000 <= j < 10000:
+            routes.append(np.zeros(0, np.int64))
+            continue
+        L = 300 if j == 123 else int(rng.integers(2, 9))
+        routes.append(rng.choice(live, L, replace=False))
+    heavy = 7
+    for j in rng.choice(np.r_[0:5000, 10000:n], 5000, replace=False):
+        if heavy not in routes[j]:
+            routes[j] = np.append(routes[j], heavy)
+    rows = np.concatenate([r for r in routes])
+    cols = np.concatenate([np.full(len(r), j) for j, r in enumerate(routes)])
+    order = np.lexsort((cols, rows))
+    row_ptr = np.zeros(m + 1, np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr).astype(np.int32)
+    c = rng.uniform(1.0, 50.0, m)
+    w = rng.uniform(0.5, 2.0, n)
+    util = (rng.random(n) < 0.3).astype(np.uint8) * I.LINEAR
+    return I.Instance("ragged", m, n, row_ptr, cols[order].astype(np.int32), c, w, util, 0.0, 10.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_binned_ragged_patterns(dtype):
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    inst = _ragged_instance().rounded(npdt)
+    deg = np.diff(inst.row_ptr)
+    assert (deg == 0).sum() == 100 and deg.max() >= 5000
+    K = 200
+    xb, lb, sb, _ = _run(inst, K, dtype, PMP_LAYOUT_BINNED)
+    xg, lg, sg, _ = _run(inst, K, dtype, PMP_LAYOUT_GATHER)
+    o = oracle.run(inst, K)
+    tol = 1e-5 if dtype == torch.float32 else 1e-10
+    print(f"ragged {dtype}: nnz={inst.nnz} binned/oracle x {rel(xb, o['x']):.2e} "
+          f"lam {rel(lb, o['lam']):.2e}; binned/gather x {rel(xb, xg):.2e}", flush=True)
+    assert rel(xb, o["x"]) <= tol and rel(lb, o["lam"]) <= tol and rel(sb, o["slack"]) <= tol
+    if dtype == torch.float32:
+        # exact FP64 sums of FP32 messages in both layouts: the same iterates
+        assert np.array_equal(xb, xg) and np.array_equal(lb, lg)
+    # streams without links sit at the maximizer of their increasing utility
+    # over the box, its upper end
+    assert np.all(xb[5000:10000] == 10.0)
