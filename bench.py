@@ -362,7 +362,7 @@ def main():
     ap.add_argument("--kernel-iters", type=int, default=40)
     ap.add_argument("--tol-max-iter", type=int, default=20000)
     ap.add_argument("--no-tol", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--cpu-single-iters", type=int, default=1,
                     help="iterations of the single-thread oracle run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
