@@ -236,8 +236,10 @@ pmp_status pmp_history(pmp_handle *h, double *out, int32_t capacity, int32_t *co
 
 /* Measurement: run k iterations (same schedule as pmp_iterate) launching
  * each pass on its own with HIP events around it on the handle's stream, and
- * return average milliseconds in host ms[4]: plain stream pass, plain link
- * pass, check stream pass, check link pass (0 when none ran). */
+ * return average milliseconds in host ms[4]: stream pass and link pass of
+ * the other iterations, stream pass and link pass of check iterations (the
+ * latter including the check's finalize kernel and, at balancing
+ * iterations, the rescale of u); 0 when none ran. */
 pmp_status pmp_time_kernels(pmp_handle *h, int32_t k, double *ms);
 
 /* Replace the weights w[n] (device memory, problem dtype, > 0), keeping each
