@@ -148,12 +148,12 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
 // eight index loads per lane are in flight; entries of longer tiles follow in
 // rounds of four 64-entry chunks, again with the loads issued first.
 //   src_off[t], src_off[t + 1]   tile t in the read layout (index array idx)
-//   dst_off[t * dst_stride]      tile t in the written layout
+//   dst_off[t]                   tile t in the written layout
 template <typename T>
 __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
-                                           const int *__restrict__ dst_off, int dst_stride,
-                                           int ntiles, const uint16_t *__restrict__ idx,
-                                           const acc_t *vals, T *__restrict__ out)
+                                           const int *__restrict__ dst_off, int ntiles,
+                                           const uint16_t *__restrict__ idx, const acc_t *vals,
+                                           T *__restrict__ out)
 {
     constexpr int W = kBinThreads / 64;
     constexpr int U = PMP_BIN_EMIT_U;
@@ -165,7 +165,7 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
         if (base + lane < mine) {
             src = src_off[t];
             cnt = src_off[t + 1] - src;
-            dst = dst_off[(long long)t * dst_stride];
+            dst = dst_off[t];
         }
         const int nt = min(64, mine - base);
         for (int i0 = 0; i0 < nt; i0 += U) {
@@ -273,7 +273,7 @@ PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
     __syncthreads();
     // tile (q, p) of the v messages and tile (p, q) of the x messages list the
     // same nonzeros in the same order
-    emit_tiles<T>(d.ov + (long long)q * d.P, d.oxq + (long long)q * d.P, 1, d.P, d.six, S, d.mx);
+    emit_tiles<T>(d.ov + (long long)q * d.P, d.oxq + (long long)q * d.P, d.P, d.six, S, d.mx);
     if (MODE == kCheck) {
         part = block_sum_n<kBinThreads>(part, sred);
         if (threadIdx.x == 0) d.spart[q] = part;
@@ -329,7 +329,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
         }
     }
     __syncthreads();
-    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, 1, d.Q, d.lix, Y, d.mv);
+    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
 }
 
 // After a check (apply = 1): apply a pending u rescale (eq. (7)), refresh
@@ -357,7 +357,7 @@ PMP_BIN_KERNEL void k_bin_emit(Dev<T> d, int apply)
         Y[i] = (acc_t)vt;
     }
     __syncthreads();
-    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, 1, d.Q, d.lix, Y, d.mv);
+    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
 }
 
 // Reverse mode in the binned layout: the two sums of a reversed iteration,
@@ -385,7 +385,7 @@ PMP_BIN_KERNEL void k_bin_adj_stream(Dev<T> d, AdjDev a, const T *xt, int last,
         S[i] = a.Sbar[j];
     }
     __syncthreads();
-    emit_tiles<double>(d.ov + (long long)q * d.P, d.oxq + (long long)q * d.P, 1, d.P, d.six, S, ms);
+    emit_tiles<double>(d.ov + (long long)q * d.P, d.oxq + (long long)q * d.P, d.P, d.six, S, ms);
 }
 
 // R Sbar per link, then (mu_prev given) the link step of the iteration
@@ -415,7 +415,7 @@ PMP_BIN_KERNEL void k_bin_adj_link(Dev<T> d, AdjDev a, const uint8_t *mu_prev, c
     }
     if (!mu_prev) return;   // ybar unchanged: its messages still hold
     __syncthreads();
-    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, 1, d.Q, d.lix, Y, my);
+    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
 }
 
 // ybar messages from a.ybar (after it changed outside k_bin_adj_link).
@@ -428,7 +428,7 @@ PMP_BIN_KERNEL void k_bin_adj_emit(Dev<T> d, AdjDev a, double *my)
     const int nl = d.lbs[p + 1] - l0;
     for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = a.ybar[l0 + i];
     __syncthreads();
-    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, 1, d.Q, d.lix, Y, my);
+    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
 }
 
 }  // namespace
