@@ -42,7 +42,9 @@ def test_binned_equals_gather_fp32(name, scale):
     same = float(np.mean(xb == xg))
     print(f"{name}: binned vs gather x {rel(xb, xg):.2e} lam {rel(lb, lg):.2e}, "
           f"bitwise-equal x fraction {same:.6f}")
-    assert rel(xb, xg) <= 1e-6 and rel(lb, lg) <= 1e-6
+    # every FP64 partial sum of FP32 messages is exact on these instances, so
+    # the LDS add order cannot show: the iterates are equal bit for bit
+    assert np.array_equal(xb, xg) and np.array_equal(lb, lg) and np.array_equal(sb, sg)
     assert abs(rb[0] - rg[0]) <= 1e-5 * rg[0] and abs(rb[1] - rg[1]) <= 1e-4 * rg[1]
 
 
