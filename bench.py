@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--cpu-single-iters", type=int, default=1,
                     help="iterations of the single-thread oracle run (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-to-tol", action="store_true",
+                    help="also run the oracle to the 1e-4 stop rule (tiny and medium only)")
     ap.add_argument("--layout", default="auto", choices=["auto", "gather", "binned"])
     ap.add_argument("--pattern", default="plain",
                     choices=["plain", "batched", "adjoint", "warmstart", "congested", "transit"],
@@ -375,6 +377,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (known bytes) for counter scaling")
     args = ap.parse_args()
+    if args.cpu_to_tol and args.config not in ("tiny", "medium"):
+        print("--cpu-to-tol is for the tiny and medium configs (the oracle would run "
+              "for hours on the larger ones)", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -473,6 +479,12 @@ def main():
                "cores": ro["threads"], "kind": "oracle",
                "sample": f"{k} iterations of the FP64 literal per-terminal oracle on the same "
                          f"{args.config} instance (setup excluded, {ro['loop_seconds']:.1f} s)"}
+        if args.cpu_to_tol:
+            # the oracle run to the stop rule itself (about 25 s for medium on
+            # 16 host threads)
+            rt = oracle.run(inst32, args.tol_max_iter, eps_abs=1e-4, stop=True)
+            cpu["to_tol"] = {"time_s": round(rt["loop_seconds"], 3),
+                             "iterations": rt["iterations"], "converged": rt["converged"]}
         if args.cpu_single_iters > 0:
             k1 = args.cpu_single_iters
             r1 = oracle.run(inst32, k1, threads=1)
