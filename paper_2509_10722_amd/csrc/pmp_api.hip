@@ -411,32 +411,41 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         d.ov = (const int *)(ws + L.ov);
         d.oxq = (const int *)(ws + L.oxq);
         d.ovp = (const int *)(ws + L.ovp);
-        const size_t tiles = (size_t)d.P * (size_t)d.Q + 1;
-        std::vector<int> hcolidx((size_t)nnz);
-        if (nnz) HIP_TRY(hipMemcpyAsync(hcolidx.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        std::vector<int> ox(tiles), ov(tiles);
-        std::vector<uint16_t> lix((size_t)nnz), six((size_t)nnz);
-        binned_build_host(hrow.data(), hcolidx.data(), m, n, bp, lbs.data(), sbs.data(), ox.data(),
-                          ov.data(), lix.data(), six.data());
         HIP_TRY(hipMemcpyAsync((void *)d.lbs, lbs.data(), ((size_t)d.P + 1) * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void *)d.sbs, sbs.data(), ((size_t)d.Q + 1) * 4, hipMemcpyHostToDevice, s));
-        // each emission walks its destination offsets in its own block order
-        std::vector<int> oxq(tiles - 1), ovp(tiles - 1);
-        for (long long p = 0; p < d.P; ++p)
-            for (long long q = 0; q < d.Q; ++q) {
-                oxq[(size_t)(q * d.P + p)] = ox[(size_t)(p * d.Q + q)];
-                ovp[(size_t)(p * d.Q + q)] = ov[(size_t)(q * d.P + p)];
+        if (binned_device_build_fits(bp) &&
+            binned_build_scratch_ints(bp) * 4 <= (size_t)(nnz + 4) * sizeof(T)) {
+            // tables built on the device; the message buffer is the scan scratch
+            binned_build_device(d.row_ptr, col_idx, bp, d.lbs, (int *)d.ox, (int *)d.ov,
+                                (int *)d.oxq, (int *)d.ovp, (uint16_t *)d.lix, (uint16_t *)d.six,
+                                (int *)d.mx, s);
+        } else {
+            const size_t tiles = (size_t)d.P * (size_t)d.Q + 1;
+            std::vector<int> hcolidx((size_t)nnz);
+            if (nnz) HIP_TRY(hipMemcpyAsync(hcolidx.data(), col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            std::vector<int> ox(tiles), ov(tiles);
+            std::vector<uint16_t> lix((size_t)nnz), six((size_t)nnz);
+            binned_build_host(hrow.data(), hcolidx.data(), m, n, bp, lbs.data(), sbs.data(),
+                              ox.data(), ov.data(), lix.data(), six.data());
+            // each emission walks its destination offsets in its own block order
+            std::vector<int> oxq(tiles - 1), ovp(tiles - 1);
+            for (long long p = 0; p < d.P; ++p)
+                for (long long q = 0; q < d.Q; ++q) {
+                    oxq[(size_t)(q * d.P + p)] = ox[(size_t)(p * d.Q + q)];
+                    ovp[(size_t)(p * d.Q + q)] = ov[(size_t)(q * d.P + p)];
+                }
+            HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.oxq, oxq.data(), (tiles - 1) * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void *)d.ovp, ovp.data(), (tiles - 1) * 4, hipMemcpyHostToDevice, s));
+            if (nnz) {
+                HIP_TRY(hipMemcpyAsync((void *)d.lix, lix.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync((void *)d.six, six.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
             }
-        HIP_TRY(hipMemcpyAsync((void *)d.ox, ox.data(), tiles * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync((void *)d.ov, ov.data(), tiles * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync((void *)d.oxq, oxq.data(), (tiles - 1) * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync((void *)d.ovp, ovp.data(), (tiles - 1) * 4, hipMemcpyHostToDevice, s));
-        if (nnz) {
-            HIP_TRY(hipMemcpyAsync((void *)d.lix, lix.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemcpyAsync((void *)d.six, six.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemsetAsync(d.mv, 0, (size_t)nnz * sizeof(T), s));   // v = 0 at the start
+            HIP_TRY(hipStreamSynchronize(s));   // the host tables go out of scope
         }
+        if (nnz) HIP_TRY(hipMemsetAsync(d.mv, 0, (size_t)nnz * sizeof(T), s));   // v = 0 at the start
         binned_configure();
         HIP_TRY(hipStreamSynchronize(s));
     }

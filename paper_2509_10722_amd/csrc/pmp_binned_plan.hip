@@ -1,6 +1,8 @@
-// Host side of the binned layout: the blocking of links and streams and the
-// tile tables (offsets and local indices) built from the CSR pattern.  The
-// kernels that use them are in pmp_binned.hip.
+// Set-up of the binned layout: the blocking of links and streams (host) and
+// the tile tables (offsets and local indices) built from the CSR pattern, on
+// the device, or on the host when the stream blocks are too many for one
+// workgroup's LDS counters.  The kernels that use the tables are in
+// pmp_binned.hip.
 #include "pmp_internal.h"
 
 #include <algorithm>
@@ -135,6 +137,104 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
                 six[ov[q * P + p] + r] = (uint16_t)(j - sbs[q]);
             }
     });
+}
+
+namespace {
+
+constexpr int kBuildThreads = 1024;
+
+// cnt[p Q + q] = nonzeros of link block p in stream block q (LDS counters).
+__global__ __launch_bounds__(kBuildThreads) void k_tile_count(const int *row_ptr,
+                                                              const int *col_idx,
+                                                              const int *lbs, int Q, int SB,
+                                                              int *cnt)
+{
+    extern __shared__ int c[];
+    const int p = blockIdx.x;
+    for (int i = threadIdx.x; i < Q; i += kBuildThreads) c[i] = 0;
+    __syncthreads();
+    const int e0 = row_ptr[lbs[p]], e1 = row_ptr[lbs[p + 1]];
+    for (int e = e0 + threadIdx.x; e < e1; e += kBuildThreads) atomicAdd(&c[col_idx[e] / SB], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < Q; i += kBuildThreads) cnt[(long long)p * Q + i] = c[i];
+}
+
+// out[c R + r] = in[r C + c] for a table of R rows of C.
+__global__ void k_transpose_int(const int *in, int R, int C, int *out)
+{
+    const long long n = (long long)R * C;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[(i % C) * R + i / C] = in[i];
+}
+
+// Local indices.  Link block p gives each of its links to one lane; a row's
+// run of nonzeros inside stream block q reserves a contiguous slot range of
+// tile (p, q) with an LDS counter and fills the same ranks of the tile in
+// both orders, so entry k of a tile is one nonzero in both and the nonzeros
+// of one link stay together (the link pass merges such runs).
+__global__ __launch_bounds__(kBuildThreads) void k_tile_place(const int *row_ptr,
+                                                              const int *col_idx,
+                                                              const int *lbs, int P, int Q,
+                                                              int SB, const int *ox,
+                                                              const int *ov, uint16_t *lix,
+                                                              uint16_t *six)
+{
+    extern __shared__ int fill[];
+    const int p = blockIdx.x;
+    for (int i = threadIdx.x; i < Q; i += kBuildThreads) fill[i] = 0;
+    __syncthreads();
+    const int l0 = lbs[p], l1 = lbs[p + 1];
+    for (int l = l0 + (int)threadIdx.x; l < l1; l += kBuildThreads) {
+        const int end = row_ptr[l + 1];
+        int e = row_ptr[l];
+        while (e < end) {
+            const int q = col_idx[e] / SB;
+            int r = e + 1;
+            while (r < end && col_idx[r] / SB == q) ++r;
+            const int base = atomicAdd(&fill[q], r - e);
+            const int xo = ox[(long long)p * Q + q] + base;
+            const int vo = ov[(long long)q * P + p] + base;
+            for (int k = e; k < r; ++k) {
+                lix[xo + (k - e)] = (uint16_t)(l - l0);
+                six[vo + (k - e)] = (uint16_t)(col_idx[k] - q * SB);
+            }
+            e = r;
+        }
+    }
+}
+
+}  // namespace
+
+bool binned_device_build_fits(const BinnedPlan &bp)
+{
+    return (size_t)bp.Q * sizeof(int) <= kBinBuildLds;
+}
+
+size_t binned_build_scratch_ints(const BinnedPlan &bp)
+{
+    return scan_scratch_ints(bp.P * bp.Q);
+}
+
+void binned_build_device(const int *row_ptr, const int *col_idx, const BinnedPlan &bp,
+                         const int *lbs, int *ox, int *ov, int *oxq, int *ovp, uint16_t *lix,
+                         uint16_t *six, int *scratch, hipStream_t s)
+{
+    const int P = bp.P, Q = bp.Q, PQ = bp.P * bp.Q;
+    const size_t lds = (size_t)Q * sizeof(int);
+    const int grid = (int)std::min<long long>(65536, ((long long)PQ + 255) / 256);
+    // counts p-major (in oxq for now), scanned into ox; q-major (in ovp),
+    // scanned into ov
+    hipLaunchKernelGGL(k_tile_count, dim3(P), dim3(kBuildThreads), lds, s, row_ptr, col_idx, lbs,
+                       Q, bp.SB, oxq);
+    launch_scan_int(oxq, PQ, ox, scratch, s);
+    hipLaunchKernelGGL(k_transpose_int, dim3(grid), dim3(256), 0, s, oxq, P, Q, ovp);
+    launch_scan_int(ovp, PQ, ov, scratch, s);
+    hipLaunchKernelGGL(k_tile_place, dim3(P), dim3(kBuildThreads), lds, s, row_ptr, col_idx, lbs,
+                       P, Q, bp.SB, ox, ov, lix, six);
+    // each side's destination offsets in its own block order
+    hipLaunchKernelGGL(k_transpose_int, dim3(grid), dim3(256), 0, s, ox, P, Q, oxq);
+    hipLaunchKernelGGL(k_transpose_int, dim3(grid), dim3(256), 0, s, ov, Q, P, ovp);
 }
 
 }  // namespace pmp

@@ -184,6 +184,21 @@ void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
                        const int *lbs, const int *sbs, int *ox, int *ov, uint16_t *lix,
                        uint16_t *six);
+// Device construction of the same tables (ox, ov, the reordered offsets
+// oxq, ovp, and lix, six) from the device CSR pattern and block starts lbs;
+// inside a tile the nonzeros are grouped by link, each link's in column
+// order.  Possible when the Q stream-block counters fit one workgroup's LDS
+// (binned_device_build_fits); scratch holds binned_build_scratch_ints ints.
+constexpr size_t kBinBuildLds = 32768;
+bool binned_device_build_fits(const BinnedPlan &bp);
+size_t binned_build_scratch_ints(const BinnedPlan &bp);
+void binned_build_device(const int *row_ptr, const int *col_idx, const BinnedPlan &bp,
+                         const int *lbs, int *ox, int *ov, int *oxq, int *ovp, uint16_t *lix,
+                         uint16_t *six, int *scratch, hipStream_t s);
+// Exclusive scan of in[n] into out[n + 1] (out[0] = 0); bsum holds
+// scan_scratch_ints(n) ints.
+size_t scan_scratch_ints(int n);
+void launch_scan_int(const int *in, int n, int *out, int *bsum, hipStream_t s);
 // mode: kPlain (x stays in the messages), kSave (x also stored, for the
 // next iteration's check), kCheck (residual partials; x stored)
 template <typename T>

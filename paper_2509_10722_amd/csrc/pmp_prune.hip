@@ -25,10 +25,6 @@
 
 namespace pmp {
 
-// Declared in pmp_kernels.hip.
-size_t scan_scratch_ints(int n);
-void launch_scan_int(const int *in, int n, int *out, int *bsum, hipStream_t s);
-
 namespace {
 
 constexpr int kWave = 64;
