@@ -9,8 +9,8 @@
 //   about nnz / P nonzeros, at most LB links; stream block q: SB consecutive
 //   streams).  mx holds x_j for every nonzero, tile by tile in p-major
 //   order; mv holds v_l in q-major order; both list a tile's nonzeros in the
-//   same order (CSR order), so entry k of tile (p, q) is the same nonzero in
-//   both.
+//   same order (grouped by link), so entry k of tile (p, q) is the same
+//   nonzero in both.
 //   stream workgroup q: add its mv entries into FP64 LDS sums by local stream
 //     index (six), run the stream epilogue (prox, relaxation), then write
 //     x_j into mx tile by tile (one wave per tile).
@@ -70,8 +70,8 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks)
 // aligned; the arrays carry 4 entries of padding), entries outside
 // [e0, e1) being masked.
 //
-// RUNS (link side): inside a tile the x messages are in CSR order, so a link
-// with many streams in the tile (a congested link) makes a long run of one
+// RUNS (link side): inside a tile the x messages are grouped by link, so a
+// link with many streams in the tile (a congested link) makes a long run of one
 // local index, and its LDS adds would all hit one address.  When some lane's
 // four entries share one index, the wave merges runs first: such a lane
 // contributes the sum of its four entries, a segmented sum over the lanes
