@@ -104,8 +104,10 @@ typedef struct {
  *   check_every  residual / stop-test period of pmp_solve (>= 1)
  *   max_iter     iteration cap of one pmp_solve call
  *   layout       sparse layout of the iteration: PMP_LAYOUT_AUTO picks
- *                PMP_LAYOUT_BINNED for FP32 problems with nnz >= 2^21 and
- *                m, n >= 256, PMP_LAYOUT_GATHER otherwise.  GATHER: CSR /
+ *                PMP_LAYOUT_BINNED for FP32 problems with nnz >= 2^21,
+ *                m, n >= 256 and tiles of 16 or more nonzeros on average,
+ *                PMP_LAYOUT_GATHER otherwise; BINNED asked for with more
+ *                than 2^28 tiles is refused (PMP_ERR_SHAPE).  GATHER: CSR /
  *                CSC passes with LDS-staged gathers (fastest while the
  *                gathered vectors stay in cache).  BINNED: R tiled into
  *                link-block x stream-block tiles with one message per

@@ -52,13 +52,34 @@ struct Layout {
     int nsb_max, nlb_max, nlc_max, nlr_max;
 };
 
+// Tiles of the binned layout for these sizes (bound of the plan).
+long long binned_tiles(int m, int n, long long nnz)
+{
+    const BinnedPlan bp = binned_plan(m, n, nnz);
+    return (long long)bp.P * bp.Q;
+}
+
+// The binned tables hold a few ints per tile; beyond this many tiles the
+// layout is refused (int offsets, and the tables would outweigh the messages).
+constexpr long long kBinMaxTiles = 1LL << 28;
+
 bool use_binned(int m, int n, long long nnz, size_t sz, int layout)
 {
     if (layout == PMP_LAYOUT_BINNED) return m > 0 && n > 0;
     if (layout == PMP_LAYOUT_GATHER) return false;
     // measured crossover on MI355X: below about 2e6 nonzeros the vectors sit
-    // in L2 and the gathers win; above, the binned passes do (1.5x at 5e6)
-    return sz == 4 && nnz >= (1LL << 21) && m >= 256 && n >= 256;
+    // in L2 and the gathers win; above, the binned passes do (1.5x at 5e6);
+    // tiles must keep 16 or more nonzeros on average to pay for themselves
+    return sz == 4 && nnz >= (1LL << 21) && m >= 256 && n >= 256 &&
+           16 * binned_tiles(m, n, nnz) <= nnz;
+}
+
+pmp_status check_binned_size(const pmp_problem *pr, const pmp_params *prm)
+{
+    if (prm && prm->layout == PMP_LAYOUT_BINNED && pr->m > 0 && pr->n > 0 &&
+        binned_tiles(pr->m, pr->n, pr->nnz) > kBinMaxTiles)
+        return fail(PMP_ERR_SHAPE, "binned layout: more than 2^28 tiles for these sizes");
+    return PMP_OK;
 }
 
 Layout plan(int m, int n, long long nnz, size_t sz, int layout)
@@ -906,6 +927,8 @@ pmp_status pmp_workspace_size(const pmp_problem *problem, const pmp_params *para
     if (!problem || !bytes) return fail(PMP_ERR_INVALID, "NULL argument");
     if (problem->m < 0 || problem->n < 0 || problem->nnz < 0 || problem->nnz >= (1LL << 31))
         return fail(PMP_ERR_SHAPE, "m, n >= 0 and 0 <= nnz < 2^31 required");
+    const pmp_status st = check_binned_size(problem, params);
+    if (st != PMP_OK) return st;
     const size_t sz = problem->dtype == PMP_F64 ? 8 : 4;
     *bytes = plan(problem->m, problem->n, problem->nnz, sz, params ? params->layout : 0).total;
     return PMP_OK;
@@ -919,6 +942,8 @@ pmp_status pmp_setup(const pmp_problem *problem, const pmp_params *params, void 
     pmp_status st = check_shape(problem);
     if (st != PMP_OK) return st;
     st = check_params(params);
+    if (st != PMP_OK) return st;
+    st = check_binned_size(problem, params);
     if (st != PMP_OK) return st;
     const size_t sz = problem->dtype == PMP_F64 ? 8 : 4;
     const Layout L = plan(problem->m, problem->n, problem->nnz, sz, params->layout);

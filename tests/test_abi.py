@@ -61,6 +61,26 @@ def test_workspace_size_and_shape_errors():
                                   ctypes.byref(b)) == pmp.PMP_ERR_SHAPE
 
 
+def test_binned_layout_size_limits():
+    from paper_2509_10722_amd import pmp
+    lib = pmp.load_library()
+    b = ctypes.c_size_t()
+    prm = pmp.params_default()
+    # a billion links and streams, few nonzeros: far too many tiles for the
+    # binned layout, which is refused when asked for and not chosen by AUTO
+    prob = pmp.pmp_problem(m=1 << 30, n=1 << 30, nnz=1 << 22, dtype=pmp.PMP_F32)
+    prm.layout = pmp.PMP_LAYOUT_BINNED
+    assert lib.pmp_workspace_size(ctypes.byref(prob), ctypes.byref(prm),
+                                  ctypes.byref(b)) == pmp.PMP_ERR_SHAPE
+    assert b"tiles" in lib.pmp_last_error()
+    prm.layout = pmp.PMP_LAYOUT_AUTO
+    assert lib.pmp_workspace_size(ctypes.byref(prob), ctypes.byref(prm), ctypes.byref(b)) == 0
+    gather = b.value
+    prm.layout = pmp.PMP_LAYOUT_GATHER
+    assert lib.pmp_workspace_size(ctypes.byref(prob), ctypes.byref(prm), ctypes.byref(b)) == 0
+    assert b.value == gather
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("rho0", 0.0, 1), ("alpha", 2.5, 1), ("mu", 1.0, 1), ("gamma", 0.5, 1),
     ("check_every", 0, 1), ("adapt_every", 15, 1),
