@@ -90,8 +90,7 @@ __device__ void stream_tile(const BDev<T> &d, int tile, T *sv, double *sred)
         const int j = s0 + (int)threadIdx.x;
         if (j < s1) {
             const int b = di.col_ptr[j] - e0, e = di.col_ptr[j + 1] - e0;
-            double acc = 0.0;
-            for (int k = b; k < e; ++k) acc += (double)sv[k];
+            const double acc = run_sum<T>(sv, b, e);
             part = stream_update<T, CHECK>(di, j, e - b, acc, rho);
         }
     } else {
@@ -124,8 +123,7 @@ __device__ void link_tile(const BDev<T> &d, int tile, T *sx, double *sred)
         const int l = l0 + (int)threadIdx.x;
         if (l < l1) {
             const int b = di.row_ptr[l] - e0, e = di.row_ptr[l + 1] - e0;
-            double acc = 0.0;
-            for (int k = b; k < e; ++k) acc += (double)sx[k];
+            const double acc = run_sum<T>(sx, b, e);
             link_update<T, MODE>(di, l, e - b, acc, r2, s2);
         }
     } else {

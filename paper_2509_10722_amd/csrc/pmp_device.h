@@ -62,6 +62,26 @@ __device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
     }
 }
 
+// FP64 sum of sh[b..e) in a fixed order: four interleaved partial sums
+// (entries b + 4i + r go to sum r), the tail into the first, then
+// (s0 + s1) + (s2 + s3).  Four independent chains hide the LDS and add
+// latency of one lane's run; every kernel that sums a staged run uses this
+// order, so their results agree bit for bit.
+template <typename T>
+__device__ __forceinline__ double run_sum(const T *sh, int b, int e)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = b;
+    for (; k + 3 < e; k += 4) {
+        s0 += (double)sh[k];
+        s1 += (double)sh[k + 1];
+        s2 += (double)sh[k + 2];
+        s3 += (double)sh[k + 3];
+    }
+    for (; k < e; ++k) s0 += (double)sh[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
 // Proximal operator of one traffic stream with L terminals and sum of
 // arguments S (Section III-E), clipped to the box.  wsig > 0: log utility
 // with weight wsig (alpha2 = false) or -w / x with weight wsig (alpha2 =

@@ -40,8 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_pass(Dev<T> d)
         const int j = s0 + (int)threadIdx.x;
         if (j < s1) {
             const int b = d.col_ptr[j] - e0, e = d.col_ptr[j + 1] - e0;
-            double acc = 0.0;
-            for (int k = b; k < e; ++k) acc += (double)sv[k];
+            const double acc = run_sum<T>(sv, b, e);
             part = stream_update<T, CHECK>(d, j, e - b, acc, rho);
         }
     } else {
@@ -86,8 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d)
         const int l = l0 + (int)threadIdx.x;
         if (l < l1) {
             const int b = d.row_ptr[l] - e0, e = d.row_ptr[l + 1] - e0;
-            double acc = 0.0;
-            for (int k = b; k < e; ++k) acc += (double)sx[k];
+            const double acc = run_sum<T>(sx, b, e);
             link_update<T, MODE>(d, l, e - b, acc, r2, s2);
         }
     }
