@@ -48,19 +48,6 @@ __device__ __forceinline__ double block_sum_d(double v, double *sh)
     return r;
 }
 
-// LDS-staged gather of a double vector over one workgroup's index range.
-__device__ __forceinline__ void gather_stage_d(const int *__restrict__ idx,
-                                               const double *__restrict__ tab, double *sh,
-                                               int cnt)
-{
-    constexpr int R = kCap / kBlock;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = r * kBlock + threadIdx.x;
-        if (i < cnt) sh[i] = tab[__builtin_nontemporal_load(idx + i)];
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const T *xt, int last)
 {
@@ -72,14 +59,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const
     const int cnt = d.col_ptr[s1] - e0;
     const double rho = d.ctl->rho;
     if (cnt <= kCap) {
-        gather_stage_d(d.row_idx + e0, a.ybar, sy, cnt);
+        gather_stage<double>(d.row_idx + e0, a.ybar, sy, cnt);
         __syncthreads();
         const int j = s0 + (int)threadIdx.x;
         if (j < s1) {
             const int b = d.col_ptr[j] - e0, e = d.col_ptr[j + 1] - e0;
-            double acc = 0.0;
-            for (int k = b; k < e; ++k) acc += sy[k];
-            adj_stream_step<T>(d, a, xt, j, e - b, acc, last, rho);
+            adj_stream_step<T>(d, a, xt, j, e - b, run_sum<double>(sy, b, e), last, rho);
         }
     } else {
         double acc = 0.0;
@@ -102,12 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_link(Dev<T> d, AdjDev a, const u
     int l = -1, deg = 0;
     double acc = 0.0;
     if (cnt <= kCap) {
-        gather_stage_d(d.col_idx + e0, a.Sbar, ss, cnt);
+        gather_stage<double>(d.col_idx + e0, a.Sbar, ss, cnt);
         __syncthreads();
         if (l0 + (int)threadIdx.x < l1) {
             l = l0 + (int)threadIdx.x;
             const int b = d.row_ptr[l] - e0, e = d.row_ptr[l + 1] - e0;
-            for (int k = b; k < e; ++k) acc += ss[k];
+            acc = run_sum<double>(ss, b, e);
             deg = e - b;
         }
     } else {
