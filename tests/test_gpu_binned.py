@@ -210,3 +210,22 @@ def test_binned_updates_and_reset_match_gather():
         s.close()
     (xb, lb, xb2), (xg, lg, xg2) = outs
     assert np.array_equal(xb, xg) and np.array_equal(lb, lg) and np.array_equal(xb2, xg2)
+
+
+def test_binned_mixed_utilities_with_alpha2():
+    """All three utilities (log, linear, -w/x) mixed on a medium-shaped
+    instance in the binned layout: the -w/x prox and the per-stream utility
+    byte it reads, against the gather layout (bit for bit) and the oracle."""
+    inst = I.medium(scale=0.1)
+    rng = np.random.default_rng(23)
+    inst.utility = rng.integers(0, 3, inst.n).astype(np.uint8)
+    inst = inst.rounded(np.float32)
+    assert (inst.utility == I.ALPHA2).any()
+    K = 150
+    xb, lb, _, _ = _run(inst, K, torch.float32, PMP_LAYOUT_BINNED)
+    xg, lg, _, _ = _run(inst, K, torch.float32, PMP_LAYOUT_GATHER)
+    o = oracle.run(inst, K)
+    print(f"mixed utilities: binned/oracle x {rel(xb, o['x']):.2e} lam {rel(lb, o['lam']):.2e}",
+          flush=True)
+    assert np.array_equal(xb, xg) and np.array_equal(lb, lg)
+    assert rel(xb, o["x"]) <= 1e-5 and rel(lb, o["lam"]) <= 1e-5
