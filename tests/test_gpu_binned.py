@@ -229,3 +229,32 @@ def test_binned_mixed_utilities_with_alpha2():
           flush=True)
     assert np.array_equal(xb, xg) and np.array_equal(lb, lg)
     assert rel(xb, o["x"]) <= 1e-5 and rel(lb, o["lam"]) <= 1e-5
+
+
+def test_binned_host_built_tables_for_many_stream_blocks():
+    """More than 8192 stream blocks (8.5e7 streams): the tile tables are
+    built on the host instead of the device; the iterates still equal the
+    gather layout's bit for bit."""
+    rng = np.random.default_rng(29)
+    m, n = 1024, 85_000_000
+    link = rng.integers(0, m, n).astype(np.int32)          # one link per stream
+    order = np.argsort(link, kind="stable").astype(np.int32)
+    row_ptr = np.zeros(m + 1, np.int32)
+    row_ptr[1:] = np.cumsum(np.bincount(link, minlength=m))
+    c = rng.uniform(1e3, 1e4, m)
+    w = rng.uniform(0.5, 2.0, n)
+    util = np.zeros(n, np.uint8)
+    inst = I.Instance("many_stream_blocks", m, n, row_ptr, order, c, w, util, 0.0, 1e4)
+    inst = inst.rounded(np.float32)
+    print(f"many stream blocks: m={m} n={n} nnz={inst.nnz}", flush=True)
+    outs = []
+    for layout in (PMP_LAYOUT_BINNED, PMP_LAYOUT_GATHER):
+        s = Solver(inst, dtype=torch.float32, layout=layout)
+        s.iterate(12)
+        x, lam, _ = s.solution()
+        outs.append((host(x), host(lam)))
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    (xb, lb), (xg, lg) = outs
+    assert np.array_equal(xb, xg) and np.array_equal(lb, lg)
