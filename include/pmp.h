@@ -24,8 +24,8 @@
  *   (a_j + b_l is the link-side copy z of terminal (j, l), zs_l that of the
  *   slack terminal; u is the scaled dual.)  Residuals ||r||, ||s|| and the
  *   stop rule of Section III-F; residual balancing of rho every
- *   `adapt_every` iterations with the rescale of u (Section III-G, eqs. (6),
- *   (7)).  Link prices are lambda = rho u; the slack is s = ps + c.
+ *   `adapt_every` iterations with the rescale of u (Section III-G, eqs. (17),
+ *   (18)).  Link prices are lambda = rho u; the slack is s = ps + c.
  *
  * Memory: every device buffer lives in one caller-owned workspace (size from
  * pmp_workspace_size).  The library allocates no device memory itself; it

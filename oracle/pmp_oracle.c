@@ -15,17 +15,17 @@
  *                link l) and one slack terminal per link; J = nnz(R) + m
  *                (Section III, bipartite graph).
  *   ADMM         p-, z- and u-updates of the scaled augmented Lagrangian on
- *                the consensus form p = z (eq. (4), eq. (5) and the three
+ *                the consensus form p = z (eq. (8), eq. (9) and the three
  *                update equations of Section III-D), with over-relaxation
  *                p+ = alpha p + (1 - alpha) z in the z- and u-updates
  *                (Section III-G, over-relaxation).
  *   prox         log, linear and slack closed forms (Section III-E).
  *   residuals    r = pbar, s = rho((p - pbar) - (p_prev - pbar_prev)), one
  *                entry per terminal; stop when both 2-norms are below
- *                eps_abs * sqrt(J) (Section III-F).
+ *                eps_abs * sqrt(J) (Section III-F, eq. (16)).
  *   rho          residual balancing every `adapt_every` iterations with the
  *                scaled dual rescaled by rho_old / rho_new (Section III-G,
- *                eqs. (6) and (7)).
+ *                eqs. (17) and (18)).
  *
  * Readings where the paper is silent or garbled (each also listed in the
  * design notes):
@@ -113,22 +113,25 @@ double orc_prox_linear(double S, int64_t L, double w, double rho, double lo, dou
 
 /* Minimum potential delay fairness (the alpha = 2 member of the alpha-fair
  * family named in Section II), f(x) = w / x for x > 0: the stationarity
- * condition -w / x^2 + rho (L x - S) = 0 is the cubic L x^3 - S x^2 - w/rho
- * = 0, which has one positive root.  Newton's method from
- * x0 = max(S/L, 0) + (w / (rho L))^(1/3), where the cubic is >= 0 and convex,
- * decreases monotonically to it. */
+ * condition -w / x^2 + rho (L x - S) = 0 is the cubic
+ * g(x) = x^2 (L x - S) - w/rho = 0.  With s+ = max(S/L, 0) and
+ * t = (w / (rho L))^(1/3): g < 0 on (0, s+] (there L x - S <= 0), g is
+ * increasing beyond s+, and g(s+ + t) >= L t^3 - w/rho = 0, so the one
+ * positive root lies in (s+, s+ + t].  Plain bisection on that bracket,
+ * halved until the midpoint no longer falls strictly inside it. */
 double orc_prox_alpha2(double S, int64_t L, double w, double rho, double lo, double hi)
 {
     if (L == 0) return hi;
     const double dl = (double)L, c = w / rho;
-    double x = (S > 0.0 ? S / dl : 0.0) + cbrt(c / dl);
-    for (int it = 0; it < 100; ++it) {
-        const double g = (dl * x - S) * x * x - c;
-        const double dg = (3.0 * dl * x - 2.0 * S) * x;
-        const double nx = x - g / dg;
-        if (!(nx < x)) break;            /* monotone: stop when it stalls */
-        x = nx;
+    double a = S > 0.0 ? S / dl : 0.0;
+    double b = a + cbrt(c / dl);
+    for (;;) {
+        const double mid = 0.5 * (a + b);
+        if (!(mid > a && mid < b)) break;
+        if (mid * mid * (dl * mid - S) - c < 0.0) a = mid;
+        else b = mid;
     }
+    double x = b;
     if (x < lo) x = lo;
     if (x > hi) x = hi;
     return x;
@@ -193,7 +196,7 @@ static void free_terminals(terminals *T)
  * Run PMP.  Outputs (any may be NULL):
  *   x[n]       stream rates
  *   lambda[m]  link prices rho * u
- *   slack[m]   s = p_slack + c (eq. (4)'s recovery relation)
+ *   slack[m]   s = p_slack + c (the recovery relation stated under eq. (8))
  *   hist_r, hist_s, hist_rho [max_iter]: per-iteration ||r||, ||s||, rho used
  *   loop_seconds  wall time of the iteration loop (setup excluded)
  *   threads_used  OpenMP threads of the parallel loops

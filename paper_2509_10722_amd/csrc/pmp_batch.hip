@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
         for (int i = 0; i < d.B; ++i) active += d.ictl[i].done ? 0 : 1;
         if (active == 0) return;   // every workgroup sees the same flags
         if (adapt > 0) {
-            // u <- (rho_old / rho_new) u where this check changed rho (eq. (7));
+            // u <- (rho_old / rho_new) u where this check changed rho (eq. (18));
             // finalize leaves ratio = 1 otherwise
             for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.g.m; l += G * blockDim.x) {
                 const double r = d.ictl[find_instance(d.link_off, d.B, l)].ratio;

@@ -332,7 +332,7 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
     emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
 }
 
-// After a check (apply = 1): apply a pending u rescale (eq. (7)), refresh
+// After a check (apply = 1): apply a pending u rescale (eq. (18)), refresh
 // v = b - u and rewrite the link messages; without a pending rescale the
 // check's link pass has written them already and nothing is done.  With
 // apply = 0 the messages are rewritten from v.

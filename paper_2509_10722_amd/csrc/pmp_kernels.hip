@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kFinThreads) void k_check_finalize(Dev<T> d, int ns
     if (threadIdx.x == 0) finalize<T>(d, delta, stop, sr, ss);
 }
 
-// u <- (rho_old / rho_new) u after a balancing step (eq. (7)); v = b - u.
+// u <- (rho_old / rho_new) u after a balancing step (eq. (18)); v = b - u.
 template <typename T>
 __global__ void k_rescale(Dev<T> d)
 {

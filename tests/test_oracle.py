@@ -266,52 +266,136 @@ def test_thread_count_does_not_change_results():
 
 # ---- over-relaxed updates as printed (Section III-G) -----------------------
 
-def _printed_updates(inst, iters, alpha, rho):
-    """Per-terminal loop over the over-relaxed PMP updates exactly as the
-    paper prints them: p = prox(z - u); z_l <- alpha (p_l - pbar_l) +
-    (1 - alpha) z_l; u_l <- u_l + alpha pbar_l (u one value per link).
-    The oracle instead projects p+ + u onto {1^T z_l = 0}; the two must
-    agree."""
+def _printed_updates(inst, iters, alpha, rho, adapt_every=0, mu=2.0, gamma=1.1,
+                     eps_abs=None, check_every=10):
+    """Per-terminal restatement of PMP exactly as the paper prints it, written
+    with NumPy over a terminal list (independent of the oracle's C loops):
+
+      p = prox(z - u)                      Section III-E closed forms
+      z_l <- alpha (p_l - pbar_l) + (1 - alpha) z_l,  u_l <- u_l + alpha pbar_l
+                                           over-relaxed updates, Section III-G
+      r_t = pbar_l(t),  s_t = rho ((p_t - pbar_l(t)) - (p_t' - pbar_l(t)'))
+                                           residuals, Section III-F (p', pbar'
+                                           the previous iteration's values)
+      stop when ||r||, ||s|| < eps_abs sqrt(J) at multiples of check_every
+      every adapt_every iterations: rho <- gamma rho if ||r|| > mu ||s||,
+      rho <- rho / gamma if ||s|| > mu ||r|| (eq. (17)), then
+      u <- (rho_old / rho_new) u (eq. (18))
+
+    u is held as one value per link (it starts at 0 and every update adds the
+    same pbar_l to all of a link's terminals).  Returns x, the prices rho u
+    and the per-iteration history of ||r||, ||s|| and the rho used, plus the
+    textbook ADMM residuals ||p - z|| and rho ||z - z_prev|| (valid as
+    residuals of the consensus form at alpha = 1) and the stop iteration."""
     m, n = inst.m, inst.n
-    terms = []                                   # (stream or -1, link)
-    for l in range(m):
-        for k in range(inst.row_ptr[l], inst.row_ptr[l + 1]):
-            terms.append((int(inst.col_idx[k]), l))
-        terms.append((-1, l))
-    z = np.zeros(len(terms))
+    row_ptr = np.asarray(inst.row_ptr, np.int64)
+    deg = np.diff(row_ptr)
+    # traffic terminals in CSR order, then one slack terminal per link
+    t_link = np.concatenate([np.repeat(np.arange(m), deg), np.arange(m)])
+    t_stream = np.concatenate([np.asarray(inst.col_idx, np.int64), -np.ones(m, np.int64)])
+    traffic = t_stream >= 0
+    Jn = len(t_link)
+    cnt = np.bincount(t_link, minlength=m).astype(float)          # |l| = d_l + 1
+    L = np.bincount(t_stream[traffic], minlength=n).astype(float)  # |sigma_j|
+    w = np.asarray(inst.w, float)
+    util = np.asarray(inst.utility)
+    z = np.zeros(Jn)
     u = np.zeros(m)
+    p_prev = np.zeros(Jn)
+    pbar_prev = np.zeros(m)
     x = np.zeros(n)
-    for _ in range(iters):
-        S = np.zeros(n); L = np.zeros(n, int)
-        for t, (j, l) in enumerate(terms):
-            if j >= 0:
-                S[j] += z[t] - u[l]; L[j] += 1
+    hist = {"r": [], "s": [], "rho": [], "r_admm": [], "s_admm": []}
+    stop_at = None
+    eps_tol = None if eps_abs is None else eps_abs * math.sqrt(Jn)
+    for k in range(1, iters + 1):
+        zeta = z - u[t_link]
+        S = np.bincount(t_stream[traffic], weights=zeta[traffic], minlength=n)
         for j in range(n):
-            if inst.utility[j] == 0:
-                q = math.sqrt(S[j] ** 2 + 4 * inst.w[j] * L[j] / rho)
-                xj = (S[j] + q) / (2 * L[j]) if S[j] >= 0 else 2 * inst.w[j] / (rho * (q - S[j]))
+            if L[j] == 0:
+                x[j] = inst.hi
+                continue
+            if util[j] == 0:
+                q = math.sqrt(S[j] ** 2 + 4 * w[j] * L[j] / rho)
+                xj = (S[j] + q) / (2 * L[j]) if S[j] >= 0 else 2 * w[j] / (rho * (q - S[j]))
             else:
-                xj = (S[j] + inst.w[j] / rho) / L[j]
+                xj = (S[j] + w[j] / rho) / L[j]
             x[j] = min(max(xj, inst.lo), inst.hi)
-        p = np.array([x[j] if j >= 0 else max(z[t] - u[l], -inst.c[l])
-                      for t, (j, l) in enumerate(terms)])
-        pbar = np.zeros(m); cnt = np.zeros(m)
-        for t, (j, l) in enumerate(terms):
-            pbar[l] += p[t]; cnt[l] += 1
-        pbar /= cnt
-        for t, (j, l) in enumerate(terms):
-            z[t] = alpha * (p[t] - pbar[l]) + (1 - alpha) * z[t]
+        p = np.where(traffic, x[np.maximum(t_stream, 0)],
+                     np.maximum(zeta, -np.asarray(inst.c, float)[t_link]))
+        pbar = np.bincount(t_link, weights=p, minlength=m) / cnt
+        z_prev = z
+        z = alpha * (p - pbar[t_link]) + (1 - alpha) * z
         u = u + alpha * pbar
-    return x, rho * u
+        r_vec = pbar[t_link]
+        s_vec = rho * ((p - pbar[t_link]) - (p_prev - pbar_prev[t_link]))
+        hist["r"].append(float(np.sqrt(np.sum(r_vec ** 2))))
+        hist["s"].append(float(np.sqrt(np.sum(s_vec ** 2))))
+        hist["rho"].append(rho)
+        hist["r_admm"].append(float(np.linalg.norm(p - z)))
+        hist["s_admm"].append(float(rho * np.linalg.norm(z - z_prev)))
+        p_prev, pbar_prev = p, pbar
+        rn, sn = hist["r"][-1], hist["s"][-1]
+        if eps_tol is not None and k % check_every == 0 and rn < eps_tol and sn < eps_tol:
+            stop_at = k
+            break
+        if adapt_every and k % adapt_every == 0:
+            new = gamma * rho if rn > mu * sn else (rho / gamma if sn > mu * rn else rho)
+            u = u * (rho / new)
+            rho = new
+    hist = {key: np.array(v) for key, v in hist.items()}
+    return x, rho * u, hist, stop_at
 
 
 @pytest.mark.parametrize("alpha", [1.0, 1.6, 1.9])
 def test_matches_printed_overrelaxed_updates(alpha):
     for inst in (I.paper_example(1.0, 3.0), I.tiny(scale=0.05)):
-        xp, lp = _printed_updates(inst, 60, alpha, 1.3)
+        xp, lp, _, _ = _printed_updates(inst, 60, alpha, 1.3)
         r = oracle.run(inst, 60, alpha=alpha, rho0=1.3, adapt_every=0)
         np.testing.assert_allclose(r["x"], xp, rtol=1e-11, atol=1e-12)
         np.testing.assert_allclose(r["lam"], lp, rtol=1e-10, atol=1e-12)
+
+
+def test_residuals_and_rho_schedule_match_restatement():
+    """Section III-F residuals and the Section III-G balancing schedule
+    (eqs. (17)-(18)) of the oracle against the per-terminal restatement:
+    300 iterations of the tiny instance at alpha = 1.6 with balancing every
+    50 iterations, which changes rho several times."""
+    inst = I.tiny()
+    K = 300
+    r = oracle.run(inst, K, alpha=1.6, history=True, adapt_every=50)
+    xp, lp, h, _ = _printed_updates(inst, K, 1.6, 1.0, adapt_every=50)
+    changes = int(np.sum(h["rho"][1:] != h["rho"][:-1]))
+    assert changes >= 2, changes
+    np.testing.assert_array_equal(r["hist_rho"], h["rho"])
+    np.testing.assert_allclose(r["hist_r"], h["r"], rtol=1e-10)
+    np.testing.assert_allclose(r["hist_s"], h["s"], rtol=1e-10)
+    np.testing.assert_allclose(r["x"], xp, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(r["lam"], lp, rtol=1e-9, atol=1e-12)
+
+
+def test_residuals_are_admm_residuals_at_alpha_one():
+    """At alpha = 1 the consensus ADMM's own residuals are r = p - z and
+    s = rho (z - z_prev) (the z-update then gives z = p - pbar); the
+    oracle's Section III-F norms must equal them, through rho changes."""
+    inst = I.tiny(scale=0.25)
+    K = 250
+    r = oracle.run(inst, K, alpha=1.0, history=True, adapt_every=50)
+    _, _, h, _ = _printed_updates(inst, K, 1.0, 1.0, adapt_every=50)
+    assert np.sum(h["rho"][1:] != h["rho"][:-1]) >= 1
+    np.testing.assert_allclose(r["hist_r"], h["r_admm"], rtol=1e-9)
+    np.testing.assert_allclose(r["hist_s"], h["s_admm"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("alpha,adapt", [(1.6, 50), (1.0, 0)])
+def test_stop_iteration_matches_restatement(alpha, adapt):
+    """The stop rule of Section III-F (both norms below 1e-4 sqrt(J) at a
+    check) fires at the same iteration in the oracle and the restatement."""
+    inst = I.tiny()
+    r = oracle.run(inst, 5000, alpha=alpha, adapt_every=adapt, stop=True, eps_abs=1e-4)
+    _, _, h, k = _printed_updates(inst, 5000, alpha, 1.0, adapt_every=adapt, eps_abs=1e-4)
+    assert r["converged"] and k is not None
+    assert r["iterations"] == k
+    assert abs(r["rho"] - h["rho"][-1]) <= 1e-15 * r["rho"]
 
 
 # ---- alpha = 2 fairness (named in Section II) -------------------------------
