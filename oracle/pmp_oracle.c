@@ -198,6 +198,10 @@ static void free_terminals(terminals *T)
  *   lambda[m]  link prices rho * u
  *   slack[m]   s = p_slack + c (the recovery relation stated under eq. (8))
  *   hist_r, hist_s, hist_rho [max_iter]: per-iteration ||r||, ||s||, rho used
+ *   hist_pn, hist_zn, hist_un [max_iter]: per-iteration ||p||, ||z|| and
+ *              ||rho u|| over all terminals (u one value per terminal), the
+ *              scales of the relative form of the stopping rule in the ADMM
+ *              reference the paper cites for convergence (Section III-F)
  *   loop_seconds  wall time of the iteration loop (setup excluded)
  *   threads_used  OpenMP threads of the parallel loops
  *   zsum_worst  max over iterations and links of |1^T z_l| / (1 + max|z_l|):
@@ -208,6 +212,7 @@ static void free_terminals(terminals *T)
 int orc_run(const orc_problem *P, const orc_params *prm,
             double *x, double *lambda, double *slack,
             double *hist_r, double *hist_s, double *hist_rho,
+            double *hist_pn, double *hist_zn, double *hist_un,
             double *zsum_worst, double *loop_seconds, int32_t *threads_used,
             orc_result *res)
 {
@@ -229,11 +234,15 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     double *r2_link = calloc((size_t)m + 1, sizeof(double));
     double *s2_link = calloc((size_t)m + 1, sizeof(double));
     double *zs_link = calloc((size_t)m + 1, sizeof(double));
+    double *pn_link = calloc((size_t)m + 1, sizeof(double));   /* sum p^2, z^2, u^2 */
+    double *zn_link = calloc((size_t)m + 1, sizeof(double));
+    double *un_link = calloc((size_t)m + 1, sizeof(double));
     double *xs = calloc((size_t)n + 1, sizeof(double));
     if (!p || !z || !u || !p_prev || !pbar_prev || !r2_link || !s2_link ||
-        !zs_link || !xs) {
+        !zs_link || !xs || !pn_link || !zn_link || !un_link) {
         free(p); free(z); free(u); free(p_prev); free(pbar_prev);
-        free(r2_link); free(s2_link); free(zs_link); free(xs); free_terminals(&T);
+        free(r2_link); free(s2_link); free(zs_link); free(xs);
+        free(pn_link); free(zn_link); free(un_link); free_terminals(&T);
         return -1;
     }
     const double alpha = prm->alpha;
@@ -285,7 +294,7 @@ int orc_run(const orc_problem *P, const orc_params *prm,
                 sum_q += pplus + u[t];
             }
             double q = sum_q / cnt;
-            double s2 = 0.0, zsum = 0.0, zmax = 0.0;
+            double s2 = 0.0, zsum = 0.0, zmax = 0.0, pn = 0.0, zn = 0.0, un = 0.0;
             for (int64_t i = a; i < b; ++i) {
                 int64_t t = T.link_terms[i];
                 double pplus = alpha * p[t] + (1.0 - alpha) * z[t];
@@ -297,16 +306,25 @@ int orc_run(const orc_problem *P, const orc_params *prm,
                 double st = rho * ((p[t] - pb) - (p_prev[t] - pbar_prev[l]));
                 s2 += st * st;
                 p_prev[t] = p[t];
+                pn += p[t] * p[t];
+                zn += znew * znew;
+                un += u[t] * u[t];
             }
             r2_link[l] = cnt * pb * pb;                       /* r_t = pbar */
             s2_link[l] = s2;
+            pn_link[l] = pn;
+            zn_link[l] = zn;
+            un_link[l] = un;
             zs_link[l] = fabs(zsum) / (1.0 + zmax);
             pbar_prev[l] = pb;
         }
-        double r2 = 0.0, s2 = 0.0;
+        double r2 = 0.0, s2 = 0.0, pn2 = 0.0, zn2 = 0.0, un2 = 0.0;
         for (int64_t l = 0; l < m; ++l) {
             r2 += r2_link[l];
             s2 += s2_link[l];
+            pn2 += pn_link[l];
+            zn2 += zn_link[l];
+            un2 += un_link[l];
             if (zs_link[l] > zsum_max) zsum_max = zs_link[l];
         }
         r_norm = sqrt(r2);
@@ -314,6 +332,9 @@ int orc_run(const orc_problem *P, const orc_params *prm,
         if (hist_r) hist_r[k - 1] = r_norm;
         if (hist_s) hist_s[k - 1] = s_norm;
         if (hist_rho) hist_rho[k - 1] = rho;
+        if (hist_pn) hist_pn[k - 1] = sqrt(pn2);
+        if (hist_zn) hist_zn[k - 1] = sqrt(zn2);
+        if (hist_un) hist_un[k - 1] = rho * sqrt(un2);
 
         /* 6. stopping criterion */
         if (prm->stop && k % prm->check_every == 0 &&
@@ -355,6 +376,7 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     }
     free(p); free(z); free(u); free(p_prev); free(pbar_prev);
     free(r2_link); free(s2_link); free(zs_link); free(xs);
+    free(pn_link); free(zn_link); free(un_link);
     free_terminals(&T);
     return 0;
 }

@@ -28,7 +28,8 @@ typedef struct {
 } orc_result;
 
 int orc_run(const orc_problem *, const orc_params *, double *, double *, double *, double *,
-            double *, double *, double *, double *, int32_t *, orc_result *);
+            double *, double *, double *, double *, double *, double *, double *, int32_t *,
+            orc_result *);
 double orc_prox_log(double, int64_t, double, double, double, double);
 double orc_prox_linear(double, int64_t, double, double, double, double);
 double orc_prox_alpha2(double, int64_t, double, double, double, double);
@@ -77,14 +78,15 @@ static void run_case(int m, int n, int busy, int util_mode)
     double *lam = malloc((size_t)m * sizeof(double)), *sl = malloc((size_t)m * sizeof(double));
     const int K = 300;
     double *hr = malloc(K * sizeof(double)), *hs = malloc(K * sizeof(double));
-    double *hp = malloc(K * sizeof(double));
+    double *hp = malloc(K * sizeof(double)), *hn = malloc(3 * K * sizeof(double));
     for (int variant = 0; variant < 4; ++variant) {
         orc_params prm = {1.0, variant == 3 ? 1.0 : 1.6, 2.0, 1.1, 1e-4, variant & 1 ? 50 : 0, 10, K,
                           variant >= 2, variant == 0 ? 1 : 3};
         double zw = 0.0, secs = 0.0;
         int32_t thr = 0;
         orc_result res;
-        REQUIRE(orc_run(&P, &prm, x, lam, sl, hr, hs, hp, &zw, &secs, &thr, &res) == 0);
+        REQUIRE(orc_run(&P, &prm, x, lam, sl, hr, hs, hp, hn, hn + K, hn + 2 * K, &zw, &secs, &thr,
+                        &res) == 0);
         REQUIRE(res.iterations >= 1 && res.iterations <= K);
         for (int j = 0; j < n; ++j) REQUIRE(isfinite(x[j]) && x[j] >= 0.0 && x[j] <= 10.0);
         REQUIRE(x[n - 1] == 10.0);      /* empty route: the upper bound */
@@ -94,9 +96,9 @@ static void run_case(int m, int n, int busy, int util_mode)
     /* NULL outputs are allowed */
     orc_params prm = {1.0, 1.6, 2.0, 1.1, 1e-4, 50, 10, 20, 0, 0};
     orc_result res;
-    REQUIRE(orc_run(&P, &prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
+    REQUIRE(orc_run(&P, &prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
     free(row_ptr); free(col_idx); free(c); free(w); free(u); free(x); free(lam); free(sl);
-    free(hr); free(hs); free(hp);
+    free(hr); free(hs); free(hp); free(hn);
 }
 
 int main(void)
@@ -116,9 +118,9 @@ int main(void)
         orc_problem P = {1, 0, 0, rp, rp, &c1, &c1, NULL, 0.0, 1.0};
         orc_params bad = {0.0, 1.6, 2.0, 1.1, 1e-4, 0, 10, 5, 0, 1};
         orc_result res;
-        REQUIRE(orc_run(&P, &bad, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == -2);
+        REQUIRE(orc_run(&P, &bad, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == -2);
         orc_params ok = {1.0, 1.6, 2.0, 1.1, 1e-4, 0, 10, 5, 0, 1};  /* no streams at all */
-        REQUIRE(orc_run(&P, &ok, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
+        REQUIRE(orc_run(&P, &ok, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
     }
     for (int mode = 0; mode < 4; ++mode) {
         run_case(40, 60, 1, mode);

@@ -304,7 +304,7 @@ def _printed_updates(inst, iters, alpha, rho, adapt_every=0, mu=2.0, gamma=1.1,
     p_prev = np.zeros(Jn)
     pbar_prev = np.zeros(m)
     x = np.zeros(n)
-    hist = {"r": [], "s": [], "rho": [], "r_admm": [], "s_admm": []}
+    hist = {"r": [], "s": [], "rho": [], "r_admm": [], "s_admm": [], "pn": [], "zn": [], "un": []}
     stop_at = None
     eps_tol = None if eps_abs is None else eps_abs * math.sqrt(Jn)
     for k in range(1, iters + 1):
@@ -333,6 +333,9 @@ def _printed_updates(inst, iters, alpha, rho, adapt_every=0, mu=2.0, gamma=1.1,
         hist["rho"].append(rho)
         hist["r_admm"].append(float(np.linalg.norm(p - z)))
         hist["s_admm"].append(float(rho * np.linalg.norm(z - z_prev)))
+        hist["pn"].append(float(np.linalg.norm(p)))
+        hist["zn"].append(float(np.linalg.norm(z)))
+        hist["un"].append(float(rho * np.sqrt(np.sum(cnt * u * u))))
         p_prev, pbar_prev = p, pbar
         rn, sn = hist["r"][-1], hist["s"][-1]
         if eps_tol is not None and k % check_every == 0 and rn < eps_tol and sn < eps_tol:
@@ -369,6 +372,9 @@ def test_residuals_and_rho_schedule_match_restatement():
     np.testing.assert_array_equal(r["hist_rho"], h["rho"])
     np.testing.assert_allclose(r["hist_r"], h["r"], rtol=1e-10)
     np.testing.assert_allclose(r["hist_s"], h["s"], rtol=1e-10)
+    np.testing.assert_allclose(r["hist_pnorm"], h["pn"], rtol=1e-10)
+    np.testing.assert_allclose(r["hist_znorm"], h["zn"], rtol=1e-10)
+    np.testing.assert_allclose(r["hist_unorm"], h["un"], rtol=1e-10)
     np.testing.assert_allclose(r["x"], xp, rtol=1e-10, atol=1e-12)
     np.testing.assert_allclose(r["lam"], lp, rtol=1e-9, atol=1e-12)
 
