@@ -28,26 +28,6 @@ namespace pmp {
 
 namespace {
 
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ double block_sum_d(double v, double *sh)
-{
-    v = wave_sum_d(v);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < kBlock / 64; ++i) r += sh[i];
-    __syncthreads();
-    return r;
-}
-
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const T *xt, int last)
 {
@@ -70,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(Dev<T> d, AdjDev a, const
         double acc = 0.0;
         for (int k = threadIdx.x; k < cnt; k += kBlock)
             acc += a.ybar[__builtin_nontemporal_load(d.row_idx + e0 + k)];
-        acc = block_sum_d(acc, sred);
+        acc = block_sum(acc, sred);
         if (threadIdx.x == 0) adj_stream_step<T>(d, a, xt, s0, cnt, acc, last, rho);
     }
 }
@@ -98,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_link(Dev<T> d, AdjDev a, const u
     } else {
         for (int k = threadIdx.x; k < cnt; k += kBlock)
             acc += a.Sbar[__builtin_nontemporal_load(d.col_idx + e0 + k)];
-        acc = block_sum_d(acc, sred);
+        acc = block_sum(acc, sred);
         if (threadIdx.x == 0) {
             l = l0;
             deg = cnt;
@@ -135,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_objective(Dev<T> d, double *part)
         if (d.util && d.util[j] == PMP_UTIL_ALPHA2) acc += -ws / x;
         else acc += ws > 0.0 ? ws * log(x) : -ws * x;
     }
-    acc = block_sum_d(acc, sred);
+    acc = block_sum(acc, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
@@ -144,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double *part, int
     __shared__ double sred[kBlock / 64];
     double acc = 0.0;
     for (int i = threadIdx.x; i < count; i += kBlock) acc += part[i];
-    acc = block_sum_d(acc, sred);
+    acc = block_sum(acc, sred);
     if (threadIdx.x == 0) *out = acc;
 }
 
@@ -186,17 +166,17 @@ __global__ void k_adj_out(Dev<T> d, AdjDev a, T *gc, T *gw)
             gc[l] = (T)a.cbar[l];
 }
 
+// Applied only when launch_check_positive found every new weight valid (the
+// utility type, kept in the sign of the stored weight, is preserved).
 template <typename T>
 __global__ void k_copy_weights(Dev<T> d, const T *w_new)
 {
-    unsigned f = 0;
+    if (d.ctl->flags & kErrWeight) return;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) {
-        const double w = (double)w_new[j];
-        if (!(w > 0.0) || !isfinite(w)) f |= kErrWeight;
+        const T w = w_new[j];
         T *ws = const_cast<T *>(d.wsig);
-        ws[j] = (double)ws[j] > 0.0 ? (T)w : (T)(-w);
+        ws[j] = (double)ws[j] > 0.0 ? w : (T)(-w);
     }
-    if (f) atomicOr(&d.ctl->flags, f);
 }
 
 inline int grid_of(long long count, int cap = 16384)
@@ -255,6 +235,7 @@ void launch_adj_out(const Dev<T> &d, const AdjDev &a, T *gc, T *gw, hipStream_t 
 template <typename T>
 void launch_copy_weights(const Dev<T> &d, const T *w_new, hipStream_t s)
 {
+    launch_check_positive<T>(w_new, d.n, d.ctl, kErrWeight, s);
     hipLaunchKernelGGL((k_copy_weights<T>), dim3(grid_of(d.n)), dim3(kBlock), 0, s, d, w_new);
 }
 

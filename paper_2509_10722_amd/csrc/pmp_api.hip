@@ -20,15 +20,11 @@ namespace {
 
 thread_local std::string g_last_error;
 
-pmp_status fail(pmp_status s, const char *fmt, ...)
+// Record the detail text of an error for pmp_last_error and return s.
+template <typename... A>
+pmp_status fail(pmp_status s, const char *fmt, A... args)
 {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return s;
+    return pmp::set_error(s, fmt, args...);
 }
 
 #define HIP_TRY(expr)                                                                     \
@@ -728,7 +724,10 @@ pmp_status forward_ckpt_impl(pmp_handle *h, int K, int s, char *ws, double *J)
         stream_pass<T>(d, t == K ? kSave : kPlain, st);   // x^K stored
         link_pass<T>(d, kPlain, 0, 0, st);
     }
+    // the K iterations count like any others (no check ran among them)
     h->iter_enq += K;
+    h->iter_fin = h->iter_enq;
+    launch_ctl_advance(h->ctl, K, st);
     launch_refresh_v<T>(d, st);   // v = b - u (the binned passes keep it in messages)
     if ((rc = copy_state<T>(h, ws + L.final_state, true)) != PMP_OK) return rc;
     if (h->n) HIP_TRY(hipMemcpyAsync(ws + L.xK, d.x, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));

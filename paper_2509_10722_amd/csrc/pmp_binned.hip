@@ -260,12 +260,13 @@ PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
                 const T xt = (T)prox_stream((double)L[g] * a[g] + (double)S[i], L[g], w[g], rho,
                                             d.lo, d.hi, a2[g]);
                 const double xn = (double)xt;
+                const T at = (T)(d.alpha * xn + (1.0 - d.alpha) * a[g]);
                 if (MODE == kCheck) {          // dual residual: sum_j L_j (dx_j)^2
                     const double dx = xn - xo[g];
-                    part += (double)L[g] * dx * dx;
+                    part += screen((double)L[g] * dx * dx, (double)at);
                 }
                 if (MODE != kPlain) d.x[j] = xt;   // otherwise x travels only in the messages
-                d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a[g]);
+                d.a[j] = at;
                 S[i] = (acc_t)xn;
             }
         }

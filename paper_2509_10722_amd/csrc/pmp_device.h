@@ -114,6 +114,15 @@ __device__ __forceinline__ double prox_stream(double S, int L, double wsig, doub
     return fmin(fmax(x, lo), hi);
 }
 
+// A check also screens the state it writes: a non-finite entry can leave the
+// residuals finite (the box clip and the slack prox's max discard NaN), so
+// it turns the partial sum into NaN, which finalize reports as
+// PMP_ERR_NUMERIC.
+__device__ __forceinline__ double screen(double part, double v)
+{
+    return isfinite(v) ? part : __builtin_nan("");
+}
+
 template <typename T>
 __device__ __forceinline__ bool is_alpha2(const Dev<T> &d, int j)
 {
@@ -128,13 +137,14 @@ __device__ __forceinline__ double stream_update(const Dev<T> &d, int j, int L, d
     const double S = (double)L * a + vsum;
     const T xt = (T)prox_stream(S, L, (double)d.wsig[j], rho, d.lo, d.hi, is_alpha2(d, j));
     const double xn = (double)xt;
+    const T at = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
     double part = 0.0;
     if (CHECK) {                       // dual residual: sum_j L_j (dx_j)^2
         const double dx = xn - (double)d.x[j];
-        part = (double)L * dx * dx;
+        part = screen((double)L * dx * dx, (double)at);
     }
     d.x[j] = xt;
-    d.a[j] = (T)(d.alpha * xn + (1.0 - d.alpha) * a);
+    d.a[j] = at;
     return part;
 }
 
@@ -167,8 +177,9 @@ __device__ __forceinline__ double link_update_in(const Dev<T> &d, int l, int deg
     const double pbar = (y + ps) / cnt;                 // link average
     const T bt = (T)(-al * pbar + (1.0 - al) * b);
     const T ut = (T)(u + al * pbar);
+    const T zt = (T)(al * (ps - pbar) + (1.0 - al) * zs);
     d.b[l] = bt;
-    d.zs[l] = (T)(al * (ps - pbar) + (1.0 - al) * zs);
+    d.zs[l] = zt;
     d.u[l] = ut;
     const T vt = (T)((double)bt - (double)ut);
     if (WRITE_V) d.v[l] = vt;
@@ -181,7 +192,7 @@ __device__ __forceinline__ double link_update_in(const Dev<T> &d, int l, int deg
         const double yp = in.yp, pp = in.pp;
         const double dpb = pbar - (yp + pp) / cnt;
         const double dy = y - yp, dps = ps - pp;
-        r2 += cnt * pbar * pbar;
+        r2 += screen(cnt * pbar * pbar, (double)bt + (double)ut + (double)zt);
         s2 += (double)deg * dpb * dpb - 2.0 * dpb * dy + (dps - dpb) * (dps - dpb);
     }
     if (MODE != kPlain) {
@@ -258,7 +269,7 @@ __device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, 
     const double rho = c->rho;
     const long long it = c->iter + delta;
     const double r = sqrt(sr);
-    const double s = rho * sqrt(fmax(ss, 0.0));
+    const double s = rho * sqrt(ss > 0.0 ? ss : (ss == ss ? 0.0 : ss));   // keeps a NaN
     c->iter = it;
     c->r_norm = r;
     c->s_norm = s;

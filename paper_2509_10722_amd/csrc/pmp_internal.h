@@ -146,6 +146,10 @@ void launch_check_vectors(const T *c, const T *w, const uint8_t *util, int m, in
                           Ctl *ctl, hipStream_t s);
 template <typename T>
 void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s);
+// Clear `bit` in ctl->flags, then set it if some v[i] is not finite and > 0.
+template <typename T>
+void launch_check_positive(const T *v, int count, Ctl *ctl, unsigned bit, hipStream_t s);
+// c <- c_new, unless launch_check_positive (queued first) rejected c_new.
 template <typename T>
 void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s);
 template <typename T>
@@ -283,6 +287,8 @@ void launch_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl, hipStre
 void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gamma,
                      int adapt_every, hipStream_t s);
 void launch_ctl_clear_done(Ctl *ctl, hipStream_t s);
+// Count k iterations run without a check (ctl->iter += k).
+void launch_ctl_advance(Ctl *ctl, long long k, hipStream_t s);
 void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double mu, double gamma, hipStream_t s);
 void launch_fill_int(int *p, int value, size_t count, hipStream_t s);
 

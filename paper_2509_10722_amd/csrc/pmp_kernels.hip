@@ -398,6 +398,8 @@ __global__ void k_ctl_clear_done(Ctl *c)
     c->status = PMP_OK;
 }
 
+__global__ void k_ctl_advance(Ctl *c, long long k) { c->iter += k; }
+
 template <typename T>
 __global__ void k_solution(Dev<T> d, T *x, T *lambda, T *slack)
 {
@@ -424,17 +426,30 @@ __global__ void k_path_prices(Dev<T> d, T *pi)
     }
 }
 
+// An update of c or w is checked in full before any of it is applied: the
+// check sets its error bit (cleared first), and the copy then returns at once
+// when the bit is set, so a rejected update leaves the instance as it was.
+__global__ void k_ctl_clear_flags(Ctl *c, unsigned mask) { c->flags &= ~mask; }
+
 template <typename T>
-__global__ void k_copy_capacity(Dev<T> d, const T *c_new)
+__global__ void k_check_positive(const T *v, int count, Ctl *ctl, unsigned bit)
 {
     const int stride = gridDim.x * blockDim.x;
     unsigned f = 0;
-    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
-        const T v = c_new[l];
-        if (!((double)v > 0.0) || !isfinite((double)v)) f |= kErrCap;
-        const_cast<T *>(d.c)[l] = v;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const double x = (double)v[i];
+        if (!(x > 0.0) || !isfinite(x)) f = bit;
     }
-    if (f) atomicOr(&d.ctl->flags, f);
+    if (f) atomicOr(&ctl->flags, f);
+}
+
+template <typename T>
+__global__ void k_copy_capacity(Dev<T> d, const T *c_new)
+{
+    if (d.ctl->flags & kErrCap) return;
+    const int stride = gridDim.x * blockDim.x;
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride)
+        const_cast<T *>(d.c)[l] = c_new[l];
 }
 
 inline int grid_for(long long count, int block = kBlock, int cap = 65536)
@@ -530,8 +545,18 @@ void launch_solution(const Dev<T> &d, T *x, T *lambda, T *slack, hipStream_t s)
 }
 
 template <typename T>
+void launch_check_positive(const T *v, int count, Ctl *ctl, unsigned bit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_clear_flags, dim3(1), dim3(1), 0, s, ctl, bit);
+    if (count > 0)
+        hipLaunchKernelGGL((k_check_positive<T>), dim3(grid_for(count, kBlock, 16384)),
+                           dim3(kBlock), 0, s, v, count, ctl, bit);
+}
+
+template <typename T>
 void launch_copy_capacity(const Dev<T> &d, const T *c_new, hipStream_t s)
 {
+    launch_check_positive<T>(c_new, d.m, d.ctl, kErrCap, s);
     hipLaunchKernelGGL((k_copy_capacity<T>), dim3(grid_for(d.m, kBlock, 16384)), dim3(kBlock), 0,
                        s, d, c_new);
 }
@@ -617,6 +642,11 @@ void launch_ctl_clear_done(Ctl *ctl, hipStream_t s)
     hipLaunchKernelGGL(k_ctl_clear_done, dim3(1), dim3(1), 0, s, ctl);
 }
 
+void launch_ctl_advance(Ctl *ctl, long long k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_advance, dim3(1), dim3(1), 0, s, ctl, k);
+}
+
 void launch_fill_int(int *p, int value, size_t count, hipStream_t s)
 {
     if (count == 0) return;
@@ -637,6 +667,7 @@ void launch_fill_int(int *p, int value, size_t count, hipStream_t s)
     template void launch_check_vectors<T>(const T *, const T *, const uint8_t *, int, int, \
                                           Ctl *, hipStream_t);                              \
     template void launch_solution<T>(const Dev<T> &, T *, T *, T *, hipStream_t);           \
+    template void launch_check_positive<T>(const T *, int, Ctl *, unsigned, hipStream_t);  \
     template void launch_copy_capacity<T>(const Dev<T> &, const T *, hipStream_t);         \
     template void launch_path_prices<T>(const Dev<T> &, T *, hipStream_t);
 
