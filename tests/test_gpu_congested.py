@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2509_10722_amd import instances as I
-from tests.gpu_util import host, rel
+from tests.gpu_util import close, host, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,8 @@ def test_congested_equal_iterations(congested, dtype_name, tol, layout):
     o = oracle.run(inst, K)
     print(f"congested {dtype_name}: x {rel(host(x), o['x']):.2e} lam {rel(host(lam), o['lam']):.2e}")
     assert rel(host(x), o["x"]) <= tol and rel(host(lam), o["lam"]) <= tol
+    bits = 64 if dtype_name == "float64" else 32
+    assert close(host(x), o["x"], bits) and close(host(lam), o["lam"], bits)
     assert abs(r - o["r_norm"]) <= 1e-4 * o["r_norm"]
 
 

@@ -16,7 +16,7 @@ import oracle
 from oracle import optimality as opt
 from oracle import prune as orc_prune
 from paper_2509_10722_amd import instances as I
-from tests.gpu_util import host, rel
+from tests.gpu_util import close, host, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -159,6 +159,7 @@ def test_path_prices_equal_iterations(dtype):
     err = rel(pi, ref)
     print(f"path prices {dtype}: {err:.2e}", flush=True)
     assert err <= (1e-10 if dtype == torch.float64 else 1e-5)
+    assert close(pi, ref, 64 if dtype == torch.float64 else 32)
 
 
 def test_path_prices_equal_marginal_utility_at_optimum():

@@ -8,7 +8,7 @@ import pytest
 import oracle
 from oracle import optimality as opt
 from paper_2509_10722_amd import instances as I
-from tests.gpu_util import host, rel
+from tests.gpu_util import close, host, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -36,9 +36,9 @@ def test_transit_equal_iterations(size):
     o = oracle.run(inst, K)
     pi_o = opt.csr_rmatvec(inst, o["lam"])
     print(f"  x {rel(x, o['x']):.2e} lam {rel(lam, o['lam']):.2e} pi {rel(pi, pi_o):.2e}")
-    assert rel(x, o["x"]) <= 1e-10
-    assert rel(lam, o["lam"]) <= 1e-10
-    assert rel(pi, pi_o) <= 1e-10
+    assert close(x, o["x"], 64)
+    assert close(lam, o["lam"], 64)
+    assert close(pi, pi_o, 64)
 
 
 def test_transit_path_prices_at_optimum():
