@@ -62,7 +62,7 @@ def _load():
         lib = ctypes.CDLL(build())
         lib.orc_run.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)] + \
-            [ctypes.c_void_p] * 12 + [ctypes.POINTER(_Result)]
+            [ctypes.c_void_p] * 13 + [ctypes.POINTER(_Result)]
         for name in ("orc_prox_log", "orc_prox_linear", "orc_prox_alpha2"):
             f = getattr(lib, name)
             f.restype = ctypes.c_double
@@ -95,12 +95,15 @@ def prox_slack(zeta, c):
 
 
 def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
-        adapt_every=50, check_every=10, stop=False, threads=0, history=False):
+        adapt_every=50, check_every=10, stop=False, threads=0, history=False,
+        branches=False):
     """Run the literal PMP on `inst` for `iters` iterations (or until the stop
     rule fires, when `stop`).  Returns a dict with x, lam (= rho u), slack,
-    iterations, r_norm, s_norm, eps_tol, rho, converged, zsum_worst and, with
-    `history`, per-iteration hist_r / hist_s / hist_rho and the norms
-    hist_pnorm / hist_znorm / hist_unorm of p, z and rho u."""
+    iterations, r_norm, s_norm, eps_tol, rho, converged, zsum_worst, with
+    `history` per-iteration hist_r / hist_s / hist_rho and the norms
+    hist_pnorm / hist_znorm / hist_unorm of p, z and rho u, and with
+    `branches` the digest of every prox branch taken (clip of each rate,
+    slack projection of each link) over the run."""
     lib = _load()
     row_ptr = np.ascontiguousarray(inst.row_ptr, dtype=np.int32)
     col_idx = np.ascontiguousarray(inst.col_idx, dtype=np.int32)
@@ -118,6 +121,7 @@ def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
     if history:
         hr, hs, hrho, hpn, hzn, hun = (np.zeros(max(1, iters)) for _ in range(6))
     zw = ctypes.c_double(0.0)
+    dig = ctypes.c_uint64(0)
     secs = ctypes.c_double(0.0)
     nthr = ctypes.c_int32(0)
     res = _Result()
@@ -125,13 +129,15 @@ def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
     rc = lib.orc_run(ctypes.byref(prob), ctypes.byref(prm), _ptr(x), _ptr(lam),
                      _ptr(slack), _ptr(hr), _ptr(hs), _ptr(hrho), _ptr(hpn), _ptr(hzn),
                      _ptr(hun), vp(zw), vp(secs),
-                     vp(nthr), ctypes.byref(res))
+                     vp(nthr), vp(dig) if branches else None, ctypes.byref(res))
     if rc != 0:
         raise RuntimeError(f"orc_run failed with code {rc}")
     out = {"x": x, "lam": lam, "slack": slack, "iterations": int(res.iterations),
            "r_norm": res.r_norm, "s_norm": res.s_norm, "eps_tol": res.eps_tol,
            "rho": res.rho, "converged": bool(res.converged), "zsum_worst": zw.value,
            "loop_seconds": secs.value, "threads": int(nthr.value)}
+    if branches:
+        out["branch_digest"] = int(dig.value)
     if history:
         k = int(res.iterations)
         out.update(hist_r=hr[:k], hist_s=hs[:k], hist_rho=hrho[:k], hist_pnorm=hpn[:k],

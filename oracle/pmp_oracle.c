@@ -207,6 +207,13 @@ static void free_terminals(terminals *T)
  *   zsum_worst  max over iterations and links of |1^T z_l| / (1 + max|z_l|):
  *               the link flow-balance indicator g_l (Section III-C) asks
  *               1^T z_l = 0 after every z-update
+ *   branch_digest  64-bit FNV-1a hash, over all iterations in order, of the
+ *               branch every prox took: per stream 0 (interior), 1 (x = lo) or
+ *               2 (x = hi), then per link 1 when the slack prox kept its
+ *               argument (z - u > -c) and 0 when it projected.  Two runs whose
+ *               digests are equal took the same branches throughout, so the
+ *               map from the data to x^K is smooth between them (used to drop
+ *               finite-difference pairs that straddle a kink).
  * Returns 0 on success, -1 on allocation failure, -2 on invalid parameters.
  */
 int orc_run(const orc_problem *P, const orc_params *prm,
@@ -214,7 +221,7 @@ int orc_run(const orc_problem *P, const orc_params *prm,
             double *hist_r, double *hist_s, double *hist_rho,
             double *hist_pn, double *hist_zn, double *hist_un,
             double *zsum_worst, double *loop_seconds, int32_t *threads_used,
-            orc_result *res)
+            uint64_t *branch_digest, orc_result *res)
 {
     if (prm->max_iter < 0 || prm->rho0 <= 0.0) return -2;
     if (prm->stop && prm->check_every <= 0) return -2;
@@ -238,13 +245,15 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     double *zn_link = calloc((size_t)m + 1, sizeof(double));
     double *un_link = calloc((size_t)m + 1, sizeof(double));
     double *xs = calloc((size_t)n + 1, sizeof(double));
+    uint8_t *branch = branch_digest ? calloc((size_t)(n + m) + 1, 1) : NULL;
     if (!p || !z || !u || !p_prev || !pbar_prev || !r2_link || !s2_link ||
-        !zs_link || !xs || !pn_link || !zn_link || !un_link) {
+        !zs_link || !xs || !pn_link || !zn_link || !un_link || (branch_digest && !branch)) {
         free(p); free(z); free(u); free(p_prev); free(pbar_prev);
         free(r2_link); free(s2_link); free(zs_link); free(xs);
-        free(pn_link); free(zn_link); free(un_link); free_terminals(&T);
+        free(pn_link); free(zn_link); free(un_link); free(branch); free_terminals(&T);
         return -1;
     }
+    uint64_t digest = 14695981039346656037ull;       /* FNV-1a offset basis */
     const double alpha = prm->alpha;
     const double eps_tol = prm->eps_abs * sqrt((double)J);
     double rho = prm->rho0;
@@ -272,12 +281,19 @@ int orc_run(const orc_problem *P, const orc_params *prm,
                 : orc_prox_alpha2(S, t1 - t0, P->w[j], rho, P->lo, P->hi);
             xs[j] = xj;
             for (int64_t t = t0; t < t1; ++t) p[t] = xj;   /* p_sigma = x 1 */
+            if (branch) branch[j] = t1 > t0 && xj == P->lo ? 1 : t1 > t0 && xj == P->hi ? 2 : 0;
         }
         #pragma omp parallel for schedule(static)
         for (int64_t l = 0; l < m; ++l) {
             int64_t t = nnz + l;
             p[t] = orc_prox_slack(z[t] - u[t], P->c[l]);
+            if (branch) branch[n + l] = z[t] - u[t] > -P->c[l];
         }
+        if (branch)
+            for (int64_t i = 0; i < n + m; ++i) {
+                digest ^= branch[i];
+                digest *= 1099511628211ull;              /* FNV-1a prime */
+            }
 
         /* 2.-4. per link: average, over-relaxed z-projection, dual update;
          * 5. residual contributions of the link's terminals */
@@ -366,6 +382,7 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     if (lambda) for (int64_t l = 0; l < m; ++l) lambda[l] = rho * u[nnz + l];
     if (slack) for (int64_t l = 0; l < m; ++l) slack[l] = p[nnz + l] + P->c[l];
     if (zsum_worst) *zsum_worst = zsum_max;
+    if (branch_digest) *branch_digest = digest;
     if (res) {
         res->iterations = k;
         res->r_norm = r_norm;
@@ -376,7 +393,7 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     }
     free(p); free(z); free(u); free(p_prev); free(pbar_prev);
     free(r2_link); free(s2_link); free(zs_link); free(xs);
-    free(pn_link); free(zn_link); free(un_link);
+    free(pn_link); free(zn_link); free(un_link); free(branch);
     free_terminals(&T);
     return 0;
 }

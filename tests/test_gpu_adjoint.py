@@ -5,6 +5,9 @@ of the printed compact updates; (ii) central finite differences of the FP64
 CPU oracle; (iii) the envelope relations dU*/dc = lambda and
 dU*/dw_j = log x_j* at large K (KKT of Section VI-B).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -19,7 +22,9 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_2509_10722_amd.pmp import Solver, pmp_objective  # noqa: E402
+from paper_2509_10722_amd.pmp import PMP_LAYOUT_BINNED, Solver, pmp_objective  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _utility_sum(inst, x):
@@ -169,3 +174,119 @@ def test_adjoint_alpha2_directional_fd():
     an = float(host(gc) @ dc + host(gw) @ dw)
     print(f"alpha2 directional derivative: adjoint {an:.10g}, FD {fd:.10g}")
     assert abs(an - fd) <= 1e-5 * max(1.0, abs(fd))
+
+
+def _golden_fd(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _fd_tol(fd, trunc, scale):
+    """Tolerance of an FP32 gradient entry against an FP64 central difference:
+    8x the difference's truncation error (estimated from its 2h repeat), 1e-5
+    relative for the FP32 rounding of the unrolled iterates carried into the
+    gradient (1e-6 normwise on the iterates after 500 iterations, tens of
+    eps32 on single entries), and an absolute floor of 1e-6 of the typical
+    entry for gradients near zero."""
+    return 8.0 * trunc + 1e-5 * abs(fd) + 1e-6 * scale
+
+
+def _direction_check(an, d, h):
+    """Directional derivative against the oracle's central difference with
+    the largest step (1e-3, 1e-5, 1e-7) whose +h and -h runs took the same
+    prox branches in every iteration (branch digest).  Along a direction every
+    coordinate moves, so with a large step some clip or slack branch changes
+    inside the interval and the difference is the mean slope across kinks,
+    not the derivative (on the full workload h = 1e-3 gives -40.6 and 1e-5
+    -37.5 against a derivative of -36.90).  Tolerance: 2e-5 relative for the
+    FP32 iterates, 8x the step's truncation estimate where there is one, and
+    4x its FD64 rounding eps |J| / h.  Returns (passed, tolerance, step)."""
+    steps = [dict(h=h, fd=d["fd"], branch_flip=d["branch_flip"], trunc=d["trunc"],
+                  rounding=0.0)] + d["small_steps"]
+    usable = [st for st in steps if not st["branch_flip"]]
+    assert usable, "every step crossed a prox kink"
+    st = usable[0]
+    tol = 2e-5 * abs(st["fd"]) + 8.0 * st.get("trunc", 0.0) + 4.0 * st["rounding"]
+    return abs(an - st["fd"]) <= tol, tol, st
+
+
+def test_adjoint_workload_fp32_binned_vs_oracle_fd():
+    """Pattern 3 at its own configuration: FP32, binned layout, K = 500 with
+    checkpoints every s = 25, fixed rho = 1, on the adjoint workload at scale
+    0.1 (m = 1e4, n = 1e5), against central differences (h = 1e-3) of the
+    FP64 oracle for 32 capacities, 32 weights and one random direction
+    (tests/golden/make_adjoint_fd.py).  Pairs whose +h and -h runs took
+    different prox branches are skipped (not a derivative there).  The
+    distance of dJ/dc to the converged prices lambda* (envelope, Section
+    VI-B) is reported: at K = 500 the iterate is far from converged."""
+    g = _golden_fd("adjoint_fd.json")
+    inst = I.adjoint(scale=0.1).rounded(np.float32)
+    assert f"m={inst.m}, n={inst.n}, nnz={inst.nnz}" in g["workload"]
+    print(f"adjoint scale 0.1: forward_ckpt({g['K']}, 25) + backward, FP32 binned", flush=True)
+    solver = Solver(inst, dtype=torch.float32, adapt_every=0, layout=PMP_LAYOUT_BINNED)
+    assert solver.layout_in_use() == "binned"
+    J = solver.forward_ckpt(g["K"], 25)
+    gc, gw = solver.backward()
+    solver.close()
+    gc, gw = host(gc), host(gw)
+    assert abs(J - g["J"]) <= 1e-6 * abs(g["J"])
+    rng = np.random.default_rng(g["seed"])
+    links = np.sort(rng.choice(inst.m, len(g["links"]), replace=False))
+    streams = np.sort(rng.choice(inst.n, len(g["streams"]), replace=False))
+    dc = rng.normal(size=inst.m)
+    dw = rng.normal(size=inst.n)
+    assert [r["index"] for r in g["links"]] == links.tolist()
+    assert [r["index"] for r in g["streams"]] == streams.tolist()
+    checked, worst = 0, 0.0
+    for grad, rows in ((gc, g["links"]), (gw, g["streams"])):
+        scale = np.sqrt(np.mean([r["fd"] ** 2 for r in rows]))
+        for r in rows:
+            if r["branch_flip"]:
+                continue
+            gi = float(grad[r["index"]])
+            tol = _fd_tol(r["fd"], r["trunc"], scale)
+            worst = max(worst, abs(gi - r["fd"]) / tol)
+            assert abs(gi - r["fd"]) <= tol, (r, gi)
+            checked += 1
+    d = g["direction"]
+    an = float(gc @ dc + gw @ dw)
+    lam_at = np.array(g["lambda_star"]["at_links"])
+    env = np.abs(gc[links] - lam_at) / np.maximum(np.abs(lam_at), 1e-12)
+    ok, tol, st = _direction_check(an, d, g["h"])
+    print(f"  {checked} of {len(g['links']) + len(g['streams'])} coordinates checked, worst "
+          f"|grad - fd| / tol {worst:.3f}; direction: adjoint {an:.10g}, FD h={st['h']:g} "
+          f"{st['fd']:.10g} (|diff| / tol {abs(an - st['fd']) / tol:.3f}; h=1e-3 gave "
+          f"{d['fd']:.10g}); envelope: "
+          f"||dJ/dc|| {np.linalg.norm(gc):.4g} vs ||lambda*|| {g['lambda_star']['norm']:.4g}, "
+          f"sampled |dJ/dc - lambda*| / lambda* median {np.median(env):.3f} max {np.max(env):.3f}")
+    assert checked >= 48
+    assert ok
+
+
+def test_adjoint_full_workload_directional_fd():
+    """The benchmarked configuration itself (scale 1: m = 1e5, n = 1e6, FP32,
+    binned, K = 500, s = 25): the directional derivative along one random
+    direction against the oracle's central differences (see
+    _direction_check)."""
+    g = _golden_fd("adjoint_fd_scale1.json")
+    inst = I.adjoint(scale=1.0).rounded(np.float32)
+    assert f"m={inst.m}, n={inst.n}, nnz={inst.nnz}" in g["workload"]
+    print(f"adjoint scale 1: forward_ckpt({g['K']}, 25) + backward, FP32 binned", flush=True)
+    solver = Solver(inst, dtype=torch.float32, adapt_every=0)
+    assert solver.layout_in_use() == "binned"
+    J = solver.forward_ckpt(g["K"], 25)
+    gc, gw = solver.backward()
+    solver.close()
+    rng = np.random.default_rng(g["seed"])
+    rng.choice(inst.m, 0, replace=False)
+    rng.choice(inst.n, 0, replace=False)
+    dc = rng.normal(size=inst.m)
+    dw = rng.normal(size=inst.n)
+    an = float(host(gc) @ dc + host(gw) @ dw)
+    d = g["direction"]
+    ok, tol, st = _direction_check(an, d, g["h"])
+    print(f"  J {J:.10g} (oracle {g['J']:.10g}); direction: adjoint {an:.10g}, FD h={st['h']:g} "
+          f"{st['fd']:.10g} (|diff| / tol {abs(an - st['fd']) / tol:.3f}; h=1e-3 gave "
+          f"{d['fd']:.10g})")
+    assert abs(J - g["J"]) <= 1e-6 * abs(g["J"])
+    assert ok
