@@ -211,6 +211,20 @@ pmp_status pmp_prune(pmp_handle *h, const uint8_t *failed, void *workspace,
                      void *w, uint8_t *utility, int32_t *link_map, int32_t *stream_map,
                      void *state, int64_t *sizes);
 
+/* For callers that cannot allocate device memory (serving loops, code that
+ * forbids hipMalloc): pmp_prune with its scratch in a fixed array of 16 MiB
+ * that the library keeps on every GPU it runs on until the process ends
+ * (its address on the device current at pmp_setup is looked up there).
+ * Arguments and results as pmp_prune, without the workspace; it allocates
+ * nothing.  PMP_ERR_SHAPE when the instance needs more scratch than the
+ * fixed maximum (4 (2n + 2m + 2) bytes plus the scans' block sums: about
+ * m + n <= 2e6).  Every call on one GPU uses that GPU's array, so calls that
+ * overlap on one GPU (several host threads, or several streams in flight)
+ * race; each call writes all of the scratch it reads. */
+pmp_status pmp_prune_noalloc(pmp_handle *h, const uint8_t *failed, int32_t *row_ptr,
+                             int32_t *col_idx, void *c, void *w, uint8_t *utility,
+                             int32_t *link_map, int32_t *stream_map, void *state, int64_t *sizes);
+
 /* Path prices (Section VI-B): pi[n] = sum over the links l of route j of
  * lambda_l = rho u_l, the price stream j pays per unit rate; at the optimum
  * pi_j = U_j'(x_j) for an interior x_j.  pi is device memory of the

@@ -202,6 +202,8 @@ struct pmp_handle {
     pmp_params prm{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    int device = 0;                // device current at pmp_setup
+    int *prune_scratch = nullptr;  // that device's fixed pruning scratch
     Dev<float> df{};
     Dev<double> dd{};
     Ctl *ctl = nullptr;            // device
@@ -963,6 +965,11 @@ pmp_status pmp_setup(const pmp_problem *problem, const pmp_params *params, void 
         pmp_destroy(h);
         return s2;
     };
+    if (hipGetDevice(&h->device) != hipSuccess)
+        return cleanup(fail(PMP_ERR_HIP, "hipGetDevice failed"));
+    // the fixed scratch of pmp_prune_noalloc on this device (looked up once)
+    if (prune_static_scratch(h->device, &h->prune_scratch) != hipSuccess)
+        return cleanup(fail(PMP_ERR_HIP, "hipGetSymbolAddress of the pruning scratch failed"));
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail(PMP_ERR_HIP, "hipStreamCreateWithFlags failed"));
     if (hipHostMalloc((void **)&h->ctl_host, sizeof(Ctl) * kSlots, hipHostMallocDefault) !=
@@ -1066,6 +1073,21 @@ pmp_status pmp_prune(pmp_handle *h, const uint8_t *failed, void *workspace,
     if (e != hipSuccess) return fail(PMP_ERR_HIP, "pruning failed: %s", hipGetErrorString(e));
     for (int i = 0; i < 3; ++i) sizes[i] = sz[i];
     return PMP_OK;
+}
+
+pmp_status pmp_prune_noalloc(pmp_handle *h, const uint8_t *failed, int32_t *row_ptr,
+                             int32_t *col_idx, void *c, void *w, uint8_t *utility,
+                             int32_t *link_map, int32_t *stream_map, void *state, int64_t *sizes)
+{
+    if (!h) return fail(PMP_ERR_INVALID, "NULL argument");
+    const size_t need = prune_scratch_ints(h->m, h->n) * 4;
+    if (need > kPruneStaticBytes)
+        return fail(PMP_ERR_SHAPE,
+                    "pmp_prune_noalloc: %zu bytes of scratch needed, the fixed maximum is %zu "
+                    "(use pmp_prune with a workspace)", need, kPruneStaticBytes);
+    if (!h->prune_scratch) return fail(PMP_ERR_STATE, "pruning scratch not set up");
+    return pmp_prune(h, failed, h->prune_scratch, need, row_ptr, col_idx, c, w, utility,
+                     link_map, stream_map, state, sizes);
 }
 
 pmp_status pmp_state_size(pmp_handle *h, size_t *bytes)

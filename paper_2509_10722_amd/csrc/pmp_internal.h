@@ -158,6 +158,11 @@ void launch_path_prices(const Dev<T> &d, T *pi, hipStream_t s);
 // Link failure compaction (pmp_prune.hip).  scratch holds
 // prune_scratch_ints(m, n) ints; sizes receives m', n', nnz'.  Synchronises s.
 size_t prune_scratch_ints(int m, int n);
+// The fixed scratch of pmp_prune_noalloc: kPruneStaticBytes on every device,
+// its address on `device` looked up once (with that device current) and
+// kept.  All its contents are written before they are read by each call.
+constexpr size_t kPruneStaticBytes = (size_t)16 << 20;
+hipError_t prune_static_scratch(int device, int **ptr);
 template <typename T>
 hipError_t prune_device(const Dev<T> &d, const uint8_t *failed, int *scratch, int *row_ptr,
                         int *col_idx, T *c, T *w, uint8_t *util, int *link_map, int *stream_map,

@@ -20,10 +20,43 @@
 //   6. c, w, utility, a, b, zs, u gathered to the new numbering.
 
 #include <algorithm>
+#include <mutex>
 
 #include "pmp_internal.h"
 
+// Scratch of pmp_prune_noalloc (the alive / renumbering / scan arrays of the
+// steps above), for callers that cannot allocate: a fixed array in device
+// memory, one per GPU, held until the process ends.  Host code never uses
+// the name of the array as an address: its per-device address comes from
+// hipGetSymbolAddress (prune_static_scratch below).
+static __device__ __align__(256) int scratch[pmp::kPruneStaticBytes / sizeof(int)];
+
 namespace pmp {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t prune_static_scratch(int device, int **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = (int *)g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -82,6 +82,8 @@ _SIGNATURES = {
     "pmp_prune_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "pmp_prune": [_P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P, _P, _P,
                   ctypes.POINTER(ctypes.c_int64)],
+    "pmp_prune_noalloc": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                          ctypes.POINTER(ctypes.c_int64)],
     "pmp_destroy": [_P],
 }
 
@@ -248,20 +250,23 @@ class Solver:
         _check(self.lib.pmp_get_path_prices(self.handle, pi.data_ptr()), "pmp_get_path_prices")
         return pi[:self.n]
 
-    def prune(self, failed, params=None):
+    def prune(self, failed, params=None, noalloc=False):
         """Link failure (Section V-D): drop the links flagged in failed[m] and
         every stream routed over one of them, on the device.  Returns
         (solver of the pruned instance warm-started from this iterate,
         link_map, stream_map) with the maps giving old indices; the pruned
-        problem's device arrays are kept as `solver.instance`."""
+        problem's device arrays are kept as `solver.instance`.  With
+        noalloc=True the compaction runs through pmp_prune_noalloc (its
+        scratch in the library's fixed array instead of a workspace)."""
         t = self.torch
         f = t.as_tensor(failed).to(dtype=t.uint8, device=self.device).contiguous()
         if f.numel() != self.m:
             raise ValueError(f"failed must have m = {self.m} entries")
-        nb = ctypes.c_size_t()
-        _check(self.lib.pmp_prune_workspace_size(self.handle, ctypes.byref(nb)),
-               "pmp_prune_workspace_size")
-        ws = t.empty(max(1, nb.value), dtype=t.uint8, device=self.device)
+        if not noalloc:
+            nb = ctypes.c_size_t()
+            _check(self.lib.pmp_prune_workspace_size(self.handle, ctypes.byref(nb)),
+                   "pmp_prune_workspace_size")
+            ws = t.empty(max(1, nb.value), dtype=t.uint8, device=self.device)
         i32 = dict(dtype=t.int32, device=self.device)
         row_ptr = t.empty(self.m + 1, **i32)
         col_idx = t.empty(max(1, self.nnz), **i32)
@@ -272,10 +277,15 @@ class Solver:
         stream_map = t.empty(max(1, self.n), **i32)
         state = t.empty(self.state_size(), dtype=t.uint8, device=self.device)
         sizes = (ctypes.c_int64 * 3)()
-        _check(self.lib.pmp_prune(self.handle, f.data_ptr(), ws.data_ptr(), nb.value,
-                                  row_ptr.data_ptr(), col_idx.data_ptr(), c.data_ptr(),
-                                  w.data_ptr(), util.data_ptr(), link_map.data_ptr(),
-                                  stream_map.data_ptr(), state.data_ptr(), sizes), "pmp_prune")
+        outs = (row_ptr.data_ptr(), col_idx.data_ptr(), c.data_ptr(), w.data_ptr(),
+                util.data_ptr(), link_map.data_ptr(), stream_map.data_ptr(), state.data_ptr(),
+                sizes)
+        if noalloc:
+            _check(self.lib.pmp_prune_noalloc(self.handle, f.data_ptr(), *outs),
+                   "pmp_prune_noalloc")
+        else:
+            _check(self.lib.pmp_prune(self.handle, f.data_ptr(), ws.data_ptr(), nb.value, *outs),
+                   "pmp_prune")
         m2, n2, nnz2 = (int(v) for v in sizes)
         pruned = PrunedInstance(m2, n2, row_ptr[:m2 + 1], col_idx[:nnz2], c[:m2], w[:n2],
                                 util[:n2], self.lo, self.hi)
