@@ -280,16 +280,28 @@ def bench_congested(args, log):
     base = instances.make(args.config, scale=args.scale)
     cong = instances.congested(base)
     out = {}
+    chunk = 2000
     for name, inst in (("uncongested", base), ("congested", cong)):
         inst = inst.rounded(np.float32)
-        s = Solver(inst, dtype=torch.float32, max_iter=args.tol_max_iter)
+        s = Solver(inst, dtype=torch.float32, max_iter=chunk)
         s.iterate(20)
         s.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = s.solve()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        # solved in chunks of `chunk` iterations (one progress line each), at
+        # most --tol-max-iter in all
+        done, dt = 0, 0.0
+        while True:
+            s.update_params(max_iter=min(chunk, args.tol_max_iter - done))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = s.solve()
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t0
+            done += r["iterations"]
+            log(f"[bench] {name}: {done} iterations, r {r['r_norm']:.3e} s {r['s_norm']:.3e} "
+                f"(tol {r['eps_tol']:.3e}), {dt:.2f} s")
+            if r["converged"] or done >= args.tol_max_iter:
+                break
+        r = dict(r, iterations=done)
         deg = np.diff(inst.row_ptr)
         out[name] = {"nnz": inst.nnz, "max_link_degree": int(deg.max()),
                      "iterations": r["iterations"], "converged": r["converged"],

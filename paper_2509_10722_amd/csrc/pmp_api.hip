@@ -366,9 +366,11 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     {
         // rows longer than kCap: chunks of kLongChunk nonzeros
         std::vector<int> cb, ce, lr, lck{0};
+        long long maxlong = 0;
         for (int l = 0; l < m; ++l) {
             const int b = hrow[(size_t)l], e = hrow[(size_t)l + 1];
             if (e - b <= kCap) continue;
+            maxlong = std::max<long long>(maxlong, e - b);
             for (int k = b; k < e; k += kLongChunk) {
                 cb.push_back(k);
                 ce.push_back(std::min(e, k + kLongChunk));
@@ -378,6 +380,21 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         }
         d.nlc = (int)cb.size();
         d.nlr = (int)lr.size();
+        // Long rows in fixed point (FP32, finite box): with F chosen so that
+        // (longest row) x hi x 2^F <= 2^62, every term and every partial sum
+        // fits an int64.  A quantum 2^-F above 2^-24 (very large hi x row
+        // length) would lose more than FP32 rounding: then FP64 sums are kept.
+        d.fx_shift = 0;
+        d.fx_scale = d.fx_inv = 1.0;
+        if (sizeof(T) == 4 && maxlong > 0 && std::isfinite(p->hi) && p->hi > 0.0) {
+            int F = (int)std::floor(62.0 - std::log2((double)maxlong * p->hi));
+            F = std::min(F, 126);
+            if (F >= 24) {
+                d.fx_shift = F;
+                d.fx_scale = std::ldexp(1.0, F);
+                d.fx_inv = std::ldexp(1.0, -F);
+            }
+        }
         if (d.nlc > L.nlc_max || d.nlr > L.nlr_max)
             return fail(PMP_ERR_SHAPE, "internal: long-row tables exceed their bound");
         if (d.nlc) {
@@ -437,7 +454,7 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
             // tables built on the device; the message buffer is the scan scratch
             binned_build_device(d.row_ptr, col_idx, bp, d.lbs, (int *)d.ox, (int *)d.ov,
                                 (int *)d.oxq, (int *)d.ovp, (uint16_t *)d.lix, (uint16_t *)d.six,
-                                (int *)d.mx, s);
+                                (int *)d.mx, d.fx_shift > 0, s);
         } else {
             const size_t tiles = (size_t)d.P * (size_t)d.Q + 1;
             std::vector<int> hcolidx((size_t)nnz);
@@ -446,7 +463,7 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
             std::vector<int> ox(tiles), ov(tiles);
             std::vector<uint16_t> lix((size_t)nnz), six((size_t)nnz);
             binned_build_host(hrow.data(), hcolidx.data(), m, n, bp, lbs.data(), sbs.data(),
-                              ox.data(), ov.data(), lix.data(), six.data());
+                              ox.data(), ov.data(), lix.data(), six.data(), d.fx_shift > 0);
             // each emission walks its destination offsets in its own block order
             std::vector<int> oxq(tiles - 1), ovp(tiles - 1);
             for (long long p = 0; p < d.P; ++p)

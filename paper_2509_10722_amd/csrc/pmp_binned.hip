@@ -78,10 +78,16 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks)
 // (segments = maximal runs of equal indices) totals each run, and the last
 // lane of a run adds it once.  The sums are FP64 sums of FP32 messages, exact
 // under the same condition as the LDS adds, so the result does not change.
-template <typename T, bool RUNS>
+//
+// FX (link side, FP32): an index carrying kLongBit belongs to a long row,
+// whose slot holds an int64 fixed-point sum instead (Dev::fx_shift): the
+// entry adds fx_term(x, fxs) with an integer atomic, and merged runs of such
+// a row add the integer sum of their terms, so the row's total does not
+// depend on the order of the adds.
+template <typename T, bool RUNS, bool FX = false>
 __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
                                            const uint16_t *__restrict__ idx, int e0, int e1,
-                                           acc_t *acc)
+                                           acc_t *acc, double fxs = 0.0)
 {
     if constexpr (sizeof(T) == 4) {
         typedef float f4 __attribute__((ext_vector_type(4)));
@@ -89,11 +95,18 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
         const f4 *m4 = (const f4 *)msg;
         const u4 *i4 = (const u4 *)idx;
         const int lane = threadIdx.x & 63;
+        auto add1 = [&](float v, unsigned key) {
+            if (FX && (key & kLongBit))
+                atomicAdd((unsigned long long *)&acc[key & kLocalMask],
+                          (unsigned long long)fx_term((double)v, fxs));
+            else
+                unsafeAtomicAdd(&acc[key & kLocalMask], (acc_t)v);
+        };
         auto add4 = [&](const f4 &v, const u4 &k, int e) {
-            if (e >= e0 && e < e1) unsafeAtomicAdd(&acc[k.x], (acc_t)v.x);
-            if (e + 1 >= e0 && e + 1 < e1) unsafeAtomicAdd(&acc[k.y], (acc_t)v.y);
-            if (e + 2 >= e0 && e + 2 < e1) unsafeAtomicAdd(&acc[k.z], (acc_t)v.z);
-            if (e + 3 >= e0 && e + 3 < e1) unsafeAtomicAdd(&acc[k.w], (acc_t)v.w);
+            if (e >= e0 && e < e1) add1(v.x, k.x);
+            if (e + 1 >= e0 && e + 1 < e1) add1(v.y, k.y);
+            if (e + 2 >= e0 && e + 2 < e1) add1(v.z, k.z);
+            if (e + 3 >= e0 && e + 3 < e1) add1(v.w, k.w);
         };
         // every lane of a wave takes the same trips (the run merge below is
         // wave-wide); a lane past the end loads nothing
@@ -113,22 +126,39 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
                                  k.z == k.w;
                 if (__ballot(uni) != 0) {
                     int key = uni ? (int)k.x : -1 - lane;   // others: segments of their own
-                    double sum = uni ? ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w)
+                    const bool lng = FX && uni && (k.x & kLongBit);
+                    double sum = uni && !lng
+                                     ? ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w)
                                      : 0.0;
+                    long long isum = 0;
+                    if (lng)
+                        isum = (fx_term((double)v.x, fxs) + fx_term((double)v.y, fxs)) +
+                               (fx_term((double)v.z, fxs) + fx_term((double)v.w, fxs));
                     if (in && !uni) add4(v, k, e);
                     const int prev = __shfl_up(key, 1, 64);
                     int head = lane == 0 || prev != key;
 #pragma unroll
                     for (int off = 1; off < 64; off <<= 1) {
                         const double so = __shfl_up(sum, off, 64);
+                        long long io = 0;
+                        if (FX) io = __shfl_up(isum, off, 64);
                         const int ho = __shfl_up(head, off, 64);
                         if (lane >= off) {
-                            if (!head) sum += so;
+                            if (!head) {
+                                sum += so;
+                                isum += io;
+                            }
                             head |= ho;
                         }
                     }
                     const int next = __shfl_down(key, 1, 64);
-                    if (uni && (lane == 63 || next != key)) unsafeAtomicAdd(&acc[key], (acc_t)sum);
+                    if (uni && (lane == 63 || next != key)) {
+                        if (lng)
+                            atomicAdd((unsigned long long *)&acc[key & kLocalMask],
+                                      (unsigned long long)isum);
+                        else
+                            unsafeAtomicAdd(&acc[key & kLocalMask], (acc_t)sum);
+                    }
                     continue;
                 }
             }
@@ -136,7 +166,7 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
         }
     } else {
         for (int e = e0 + threadIdx.x; e < e1; e += kBinThreads)
-            unsafeAtomicAdd(&acc[idx[e]], (acc_t)__builtin_nontemporal_load(msg + e));
+            unsafeAtomicAdd(&acc[idx[e] & kLocalMask], (acc_t)__builtin_nontemporal_load(msg + e));
     }
 }
 
@@ -149,7 +179,11 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
 // rounds of four 64-entry chunks, again with the loads issued first.
 //   src_off[t], src_off[t + 1]   tile t in the read layout (index array idx)
 //   dst_off[t]                   tile t in the written layout
-template <typename T>
+// LONG: the local indices may carry kLongBit (link side of a problem with
+// fixed-point long rows), which is masked off where the LDS value is read.
+// (Masked right at the load, the compiler waits for each index load before
+// issuing the next: 17% slower passes on the large workload.)
+template <typename T, bool LONG = false>
 __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
                                            const int *__restrict__ dst_off, int ntiles,
                                            const uint16_t *__restrict__ idx, const acc_t *vals,
@@ -189,7 +223,7 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
             for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int r = 0; r < 2; ++r)
-                    if (id[u][r] >= 0) out[d_u[u] + lane + 64 * r] = (T)vals[id[u][r]];
+                    if (id[u][r] >= 0) out[d_u[u] + lane + 64 * r] = (T)vals[LONG ? id[u][r] & kLocalMask : id[u][r]];
             // long tiles: four chunks of 64 entries per round, loads first
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -202,7 +236,7 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
                     }
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        if (it[r] >= 0) out[d_u[u] + k0 + 64 * r] = (T)vals[it[r]];
+                        if (it[r] >= 0) out[d_u[u] + k0 + 64 * r] = (T)vals[LONG ? it[r] & kLocalMask : it[r]];
                 }
         }
     }
@@ -292,7 +326,9 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
     const int nl = d.lbs[p + 1] - l0;
     for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = 0.0;
     __syncthreads();
-    accumulate<T, PMP_BIN_RUNS>(d.mx, d.lix, d.ox[(long long)p * d.Q], d.ox[(long long)(p + 1) * d.Q], Y);
+    const int e0 = d.ox[(long long)p * d.Q], e1 = d.ox[(long long)(p + 1) * d.Q];
+    if (sizeof(T) == 4 && d.fx_shift) accumulate<T, PMP_BIN_RUNS, true>(d.mx, d.lix, e0, e1, Y, d.fx_scale);
+    else accumulate<T, PMP_BIN_RUNS>(d.mx, d.lix, e0, e1, Y);
     __syncthreads();
     double r2 = 0.0, s2 = 0.0;
     constexpr int G = MODE == kCheck ? 1 : PMP_BIN_EPI;   // a check carries more inputs
@@ -314,7 +350,8 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
             if (i < nl) {
                 const int l = l0 + i;
                 // v goes out in the messages; a check also stores it
-                const double y = (double)Y[i];
+                double y = (double)Y[i];
+                if (d.fx_shift && deg[g] > kCap) y = (double)__double_as_longlong(Y[i]) * d.fx_inv;
                 Y[i] = (acc_t)(MODE == kCheck
                                    ? link_update_in<T, MODE, true>(d, l, deg[g], y, in[g], r2, s2)
                                    : link_update_in<T, MODE, false>(d, l, deg[g], y, in[g], r2, s2));
@@ -330,7 +367,8 @@ PMP_BIN_KERNEL void k_bin_link(Dev<T> d)
         }
     }
     __syncthreads();
-    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
+    if (d.fx_shift) emit_tiles<T, true>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
+    else emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
 }
 
 // After a check (apply = 1): apply a pending u rescale (eq. (18)), refresh
@@ -358,7 +396,8 @@ PMP_BIN_KERNEL void k_bin_emit(Dev<T> d, int apply)
         Y[i] = (acc_t)vt;
     }
     __syncthreads();
-    emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
+    if (d.fx_shift) emit_tiles<T, true>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
+    else emit_tiles<T>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, d.mv);
 }
 
 // Reverse mode in the binned layout: the two sums of a reversed iteration,
@@ -416,7 +455,8 @@ PMP_BIN_KERNEL void k_bin_adj_link(Dev<T> d, AdjDev a, const uint8_t *mu_prev, c
     }
     if (!mu_prev) return;   // ybar unchanged: its messages still hold
     __syncthreads();
-    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
+    if (d.fx_shift) emit_tiles<double, true>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
+    else emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
 }
 
 // ybar messages from a.ybar (after it changed outside k_bin_adj_link).
@@ -429,7 +469,8 @@ PMP_BIN_KERNEL void k_bin_adj_emit(Dev<T> d, AdjDev a, double *my)
     const int nl = d.lbs[p + 1] - l0;
     for (int i = threadIdx.x; i < nl; i += kBinThreads) Y[i] = a.ybar[l0 + i];
     __syncthreads();
-    emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
+    if (d.fx_shift) emit_tiles<double, true>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
+    else emit_tiles<double>(d.ox + (long long)p * d.Q, d.ovp + (long long)p * d.Q, d.Q, d.lix, Y, my);
 }
 
 }  // namespace

@@ -89,7 +89,7 @@ void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &
 
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
                        const int *lbs, const int *sbs, int *ox, int *ov, uint16_t *lix,
-                       uint16_t *six)
+                       uint16_t *six, int mark_long)
 {
     const long long P = bp.P, Q = bp.Q;
     (void)m;
@@ -128,14 +128,16 @@ void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, con
     over_blocks([&](long long p) {
         int *c = cnt.data() + p * Q;
         std::fill(c, c + Q, 0);
-        for (int l = lbs[p]; l < lbs[p + 1]; ++l)
+        for (int l = lbs[p]; l < lbs[p + 1]; ++l) {
+            const uint16_t tag = mark_long && row_ptr[l + 1] - row_ptr[l] > kCap ? kLongBit : 0;
             for (int k = row_ptr[l]; k < row_ptr[l + 1]; ++k) {
                 const int j = col_idx[k];
                 const long long q = j / bp.SB;
                 const int r = c[q]++;   // rank in the tile, CSR order
-                lix[ox[p * Q + q] + r] = (uint16_t)(l - lbs[p]);
+                lix[ox[p * Q + q] + r] = (uint16_t)((l - lbs[p]) | tag);
                 six[ov[q * P + p] + r] = (uint16_t)(j - sbs[q]);
             }
+        }
     });
 }
 
@@ -178,7 +180,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_tile_place(const int *row_ptr
                                                               const int *lbs, int P, int Q,
                                                               int SB, const int *ox,
                                                               const int *ov, uint16_t *lix,
-                                                              uint16_t *six)
+                                                              uint16_t *six, int mark_long)
 {
     extern __shared__ int fill[];
     const int p = blockIdx.x;
@@ -188,6 +190,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_tile_place(const int *row_ptr
     for (int l = l0 + (int)threadIdx.x; l < l1; l += kBuildThreads) {
         const int end = row_ptr[l + 1];
         int e = row_ptr[l];
+        const uint16_t tag = mark_long && end - e > kCap ? kLongBit : 0;
         while (e < end) {
             const int q = col_idx[e] / SB;
             int r = e + 1;
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_tile_place(const int *row_ptr
             const int xo = ox[(long long)p * Q + q] + base;
             const int vo = ov[(long long)q * P + p] + base;
             for (int k = e; k < r; ++k) {
-                lix[xo + (k - e)] = (uint16_t)(l - l0);
+                lix[xo + (k - e)] = (uint16_t)((l - l0) | tag);
                 six[vo + (k - e)] = (uint16_t)(col_idx[k] - q * SB);
             }
             e = r;
@@ -218,7 +221,7 @@ size_t binned_build_scratch_ints(const BinnedPlan &bp)
 
 void binned_build_device(const int *row_ptr, const int *col_idx, const BinnedPlan &bp,
                          const int *lbs, int *ox, int *ov, int *oxq, int *ovp, uint16_t *lix,
-                         uint16_t *six, int *scratch, hipStream_t s)
+                         uint16_t *six, int *scratch, int mark_long, hipStream_t s)
 {
     const int P = bp.P, Q = bp.Q, PQ = bp.P * bp.Q;
     const size_t lds = (size_t)Q * sizeof(int);
@@ -231,7 +234,7 @@ void binned_build_device(const int *row_ptr, const int *col_idx, const BinnedPla
     hipLaunchKernelGGL(k_transpose_int, dim3(grid), dim3(256), 0, s, oxq, P, Q, ovp);
     launch_scan_int(ovp, PQ, ov, scratch, s);
     hipLaunchKernelGGL(k_tile_place, dim3(P), dim3(kBuildThreads), lds, s, row_ptr, col_idx, lbs,
-                       P, Q, bp.SB, ox, ov, lix, six);
+                       P, Q, bp.SB, ox, ov, lix, six, mark_long);
     // each side's destination offsets in its own block order
     hipLaunchKernelGGL(k_transpose_int, dim3(grid), dim3(256), 0, s, ox, P, Q, oxq);
     hipLaunchKernelGGL(k_transpose_int, dim3(grid), dim3(256), 0, s, ov, Q, P, ovp);

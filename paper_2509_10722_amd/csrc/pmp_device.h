@@ -38,6 +38,30 @@ __device__ __forceinline__ double block_sum_n(double v, double *sh)
 
 __device__ __forceinline__ double block_sum(double v, double *sh) { return block_sum_n<kBlock>(v, sh); }
 
+// Fixed-point term of a long row's sum (Dev::fx_shift): x 2^F rounded to an
+// integer (x >= 0 and below 2^62 / (row length) after scaling, by the choice of F).
+__device__ __forceinline__ long long fx_term(double x, double scale)
+{
+    return __double2ll_rn(x * scale);
+}
+
+// Exact int64 sum over a workgroup of kBlock threads (valid in thread 0);
+// `sh` holds kBlock / 64 doubles, reused as int64.
+__device__ __forceinline__ long long block_sum_ll(long long v, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    long long *s = (long long *)sh;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) s[wid] = v;
+    __syncthreads();
+    long long r = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) r += s[i];
+    __syncthreads();
+    return r;
+}
+
 // Stage tab[idx[i]] for i < cnt into LDS.  Every lane first loads its share of
 // the index stream, then issues all of its gathers, then writes LDS, so up to
 // kCap / kBlock gathers per lane are in flight together.

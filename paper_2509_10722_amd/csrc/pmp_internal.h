@@ -92,6 +92,14 @@ struct Dev {
     const int *lr_row, *lr_ck;      // [nlr], [nlr + 1] long rows and their chunks
     double *rpart;                  // [nlc] chunk sums
     double lo, hi, alpha;
+    // Long rows (more than kCap nonzeros, congested links) of FP32 problems
+    // with a finite box are summed in fixed point: each rate x becomes the
+    // integer llrint(x 2^fx_shift) and the row sum is the exact int64 sum of
+    // those, times 2^-fx_shift.  Integer sums do not depend on the order of
+    // the adds, so these rows come out the same in both layouts and in every
+    // run.  fx_shift = 0: plain FP64 sums.
+    int fx_shift;
+    double fx_scale, fx_inv;        // 2^fx_shift, 2^-fx_shift
     Ctl *ctl;
     HistEntry *hist;
     // Binned message layout (pmp_binned.hip); P link blocks of at most LB
@@ -177,6 +185,11 @@ hipError_t prune_device(const Dev<T> &d, const uint8_t *failed, int *scratch, in
 #endif
 constexpr int kBinThreads = PMP_BIN_THREADS;       // threads per binned workgroup
 constexpr int kBinMaxBlock = PMP_BIN_MAX_BLOCK;    // links / streams per binned workgroup
+// A link-side local index (lix) carries kLongBit when its link is a long row
+// (more than kCap nonzeros) whose sum is formed in fixed point (Dev::fx_shift).
+constexpr uint16_t kLongBit = 0x8000;
+constexpr uint16_t kLocalMask = 0x7fff;
+static_assert(kBinMaxBlock <= kLocalMask, "local indices must leave the top bit free");
 struct BinnedPlan {
     int P, Q;     // link blocks, stream blocks
     int LB, SB;   // most links / streams in one block (LDS sums per workgroup)
@@ -190,9 +203,10 @@ BinnedPlan binned_plan(int m, int n, long long nnz);
 void binned_blocks(const int *row_ptr, int m, int n, long long nnz, BinnedPlan &bp, int *lbs,
                    int *sbs);
 // Host construction of ox, ov, lix, six from the CSR pattern and the blocks.
+// With mark_long, lix entries of rows longer than kCap carry kLongBit.
 void binned_build_host(const int *row_ptr, const int *col_idx, int m, int n, const BinnedPlan &bp,
                        const int *lbs, const int *sbs, int *ox, int *ov, uint16_t *lix,
-                       uint16_t *six);
+                       uint16_t *six, int mark_long);
 // Device construction of the same tables (ox, ov, the reordered offsets
 // oxq, ovp, and lix, six) from the device CSR pattern and block starts lbs;
 // inside a tile the nonzeros are grouped by link, each link's in column
@@ -203,7 +217,7 @@ bool binned_device_build_fits(const BinnedPlan &bp);
 size_t binned_build_scratch_ints(const BinnedPlan &bp);
 void binned_build_device(const int *row_ptr, const int *col_idx, const BinnedPlan &bp,
                          const int *lbs, int *ox, int *ov, int *oxq, int *ovp, uint16_t *lix,
-                         uint16_t *six, int *scratch, hipStream_t s);
+                         uint16_t *six, int *scratch, int mark_long, hipStream_t s);
 // Exclusive scan of in[n] into out[n + 1] (out[0] = 0); bsum holds
 // scan_scratch_ints(n) ints.
 size_t scan_scratch_ints(int n);

@@ -66,8 +66,17 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d)
     __shared__ double sred[kBlock / 64];
     const int blk = blockIdx.x;
     if (blk >= d.nlb) {
-        // one chunk of a long row: a partial sum in a fixed order
+        // one chunk of a long row: a partial sum in a fixed order, or the
+        // exact fixed-point sum (kept as int64 bits in rpart)
         const int c = blk - d.nlb;
+        if (d.fx_shift) {
+            long long acc = 0;
+            for (int k = d.lck_beg[c] + threadIdx.x; k < d.lck_end[c]; k += kBlock)
+                acc += fx_term((double)d.x[ld_stream(d.col_idx + k)], d.fx_scale);
+            acc = block_sum_ll(acc, sred);
+            if (threadIdx.x == 0) ((long long *)d.rpart)[c] = acc;
+            return;
+        }
         double acc = 0.0;
         for (int k = d.lck_beg[c] + threadIdx.x; k < d.lck_end[c]; k += kBlock)
             acc += (double)d.x[ld_stream(d.col_idx + k)];
@@ -108,7 +117,13 @@ __global__ void k_long_rows(Dev<T> d)
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.nlr; r += gridDim.x * blockDim.x) {
         const int l = d.lr_row[r];
         double y = 0.0;
-        for (int c = d.lr_ck[r]; c < d.lr_ck[r + 1]; ++c) y += d.rpart[c];
+        if (d.fx_shift) {
+            long long t = 0;
+            for (int c = d.lr_ck[r]; c < d.lr_ck[r + 1]; ++c) t += ((const long long *)d.rpart)[c];
+            y = (double)t * d.fx_inv;
+        } else {
+            for (int c = d.lr_ck[r]; c < d.lr_ck[r + 1]; ++c) y += d.rpart[c];
+        }
         double r2 = 0.0, s2 = 0.0;
         link_update<T, MODE>(d, l, d.row_ptr[l + 1] - d.row_ptr[l], y, r2, s2);
         if (MODE == kCheck) {

@@ -90,7 +90,7 @@ static void check_binned(const Csr &a)
     std::vector<int> ox(tiles + 1), ov(tiles + 1);
     std::vector<uint16_t> lix((size_t)nnz + 4), six((size_t)nnz + 4);
     binned_build_host(a.row_ptr.data(), a.col_idx.data(), a.m, a.n, bp, lbs.data(), sbs.data(),
-                      ox.data(), ov.data(), lix.data(), six.data());
+                      ox.data(), ov.data(), lix.data(), six.data(), 1);
     REQUIRE(ox[0] == 0 && ox[tiles] == nnz && ov[0] == 0 && ov[tiles] == nnz);
     for (size_t t = 0; t < tiles; ++t) REQUIRE(ox[t] <= ox[t + 1] && ov[t] <= ov[t + 1]);
     // every nonzero appears once, at its own link and stream
@@ -101,7 +101,10 @@ static void check_binned(const Csr &a)
             const int len = ox[tx + 1] - ox[tx];
             REQUIRE(len == ov[tv + 1] - ov[tv]);
             for (int k = 0; k < len; ++k) {
-                const int l = lbs[(size_t)p] + lix[(size_t)ox[tx] + k];
+                const uint16_t code = lix[(size_t)ox[tx] + k];
+                const int l = lbs[(size_t)p] + (code & kLocalMask);
+                REQUIRE(((code & kLongBit) != 0) ==
+                        (a.row_ptr[(size_t)l + 1] - a.row_ptr[(size_t)l] > kCap));
                 const int j = sbs[(size_t)q] + six[(size_t)ov[tv] + k];
                 REQUIRE(l < lbs[(size_t)p + 1] && j < sbs[(size_t)q + 1]);
                 REQUIRE(std::binary_search(a.col_idx.begin() + a.row_ptr[(size_t)l],
