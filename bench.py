@@ -63,6 +63,19 @@ def load_traffic(kernel, layout, workload):
     return t.get("bytes_per_launch")
 
 
+def calibrate_copy(log):
+    """An elementwise kernel that reads and writes 1 GiB each (known bytes),
+    the scale for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration: 3 x torch.mul over {src.numel() * 4} bytes in and out")
+    del src, dst
+
+
 def bench_batched(args, log):
     """Pattern 2: the batched transit workload (64 instances, m log-uniform
     on [1e3, 1e5], n = 5m, degraded capacities) solved to the 1e-4 rule by
@@ -73,6 +86,8 @@ def bench_batched(args, log):
     from paper_2509_10722_amd import autotune, instances
     from paper_2509_10722_amd.pmp import BatchSolver, Solver
 
+    if args.calibrate_copy:
+        calibrate_copy(log)
     insts = [i.rounded(np.float32) for i in instances.batched(scale=args.scale)]
     tot = {"m": sum(i.m for i in insts), "n": sum(i.n for i in insts),
            "nnz": sum(i.nnz for i in insts)}
@@ -82,19 +97,31 @@ def bench_batched(args, log):
     else:
         opts = autotune.cached_options(torch)
     caps = list(opts.tile_cap) + [int(opts.wg_per_cu)]
-    b = BatchSolver(insts, dtype=torch.float32, options=opts)
-    b.solve(20)                     # warm-up: graph capture, first touch
-    b.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = b.solve(args.tol_max_iter)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    b.close()
+
+    def batched_solve(profile):
+        opts.profile = int(profile)
+        b = BatchSolver(insts, dtype=torch.float32, options=opts)
+        b.solve(20)                     # warm-up: graph capture, first touch
+        b.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = b.solve(args.tol_max_iter)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        prof = b.profile() if profile else None
+        b.close()
+        return t, res, prof
+
+    tb, res, _ = batched_solve(False)
     iters = [r["iterations"] for r in res]
     conv = sum(r["converged"] for r in res)
     log(f"[bench] batched solve: {tb:.3f} s, {conv}/{len(insts)} converged, "
         f"iterations {min(iters)}..{max(iters)}")
+    if args.batch_only:   # one solve and nothing else (for counter runs)
+        return
+    # the same solve again with the kernel's phase clocks on
+    tprof, _, phases = batched_solve(True)
+    log(f"[bench] phases (ms per workgroup, solve {tprof:.3f} s): {phases}")
     # the same instances one by one (graph-replayed pmp_solve each)
     tp = 0.0
     plain_iters = []
@@ -122,6 +149,7 @@ def bench_batched(args, log):
         "iterations": {"min": int(min(iters)), "median": int(np.median(iters)),
                        "max": int(max(iters))},
         "model_gbs": round(work / tb / 1e9, 2),
+        "phases_ms": {k: round(v, 2) for k, v in phases.items()},
     }
     print(json.dumps(line), flush=True)
 
@@ -394,6 +422,8 @@ def main():
                     help="plain: the large workload (the default line); batched / adjoint: "
                          "the two training-system patterns, one JSON line each")
     ap.add_argument("--tune", action="store_true", help="batched: run the tile autotuner first")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batched: one warm-up and one timed solve only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -428,14 +458,7 @@ def main():
         return bench_transit(args, log)
 
     if args.calibrate_copy:
-        # an elementwise kernel that reads and writes 1 GiB each (known bytes)
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration: 3 x torch.mul over {src.numel() * 4} bytes in and out")
-        del src, dst
+        calibrate_copy(log)
 
     t0 = time.perf_counter()
     inst = instances.make(args.config, scale=args.scale)

@@ -304,6 +304,7 @@ typedef struct {
     int32_t reorder_streams;
     int32_t wg_per_cu;      /* resident workgroups per CU in the persistent grid
                                (1..8, capped by occupancy; 0 = 2) */
+    int32_t profile;        /* 1: time the kernel's phases (pmp_batch_profile) */
 } pmp_batch_options;
 
 /* Defaults (tuned on MI355X for transit batches): classes at m = 1e4 and
@@ -331,6 +332,12 @@ pmp_status pmp_batch_get_solution(pmp_batch *b, int32_t index, void *x, void *la
                                   void *slack);
 /* Back to the all-zero start, rho = rho0, for every instance. */
 pmp_status pmp_batch_reset(pmp_batch *b);
+/* Time of the last pmp_batch_solve's kernel by phase, averaged over its
+ * workgroups, in ms (host ms[6]): stream tiles, wait at the grid barrier
+ * after them, link tiles, wait after them, check finalize with its barrier,
+ * rho rescale with its barrier (device wall clock).  PMP_ERR_STATE unless
+ * the batch was set up with options.profile = 1. */
+pmp_status pmp_batch_profile(pmp_batch *b, double *ms);
 pmp_status pmp_batch_destroy(pmp_batch *b);
 
 /* The layout chosen at setup (PMP_LAYOUT_GATHER or PMP_LAYOUT_BINNED). */

@@ -161,6 +161,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
     __shared__ T sv[kCap];
     __shared__ double sred[kBlock / 64];
     const unsigned G = gridDim.x;
+    // phase clocks (profile only): thread 0 adds each phase's duration
+    unsigned long long ph[kBatchPhases] = {};
+    unsigned long long tmark = d.prof ? wall_clock64() : 0;
+    auto lap = [&](int phase) {
+        if (d.prof && threadIdx.x == 0) {
+            const unsigned long long now = wall_clock64();
+            ph[phase] += now - tmark;
+            tmark = now;
+        }
+    };
     // a solve call continues every instance from its current state
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.B; i += G * blockDim.x)
         d.ictl[i].done = 0;
@@ -169,17 +179,22 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
     for (int it = 1; it <= max_iter; ++it) {
         const bool check = it % ce == 0 || it == max_iter;
         const bool save = !check && ((it + 1) % ce == 0 || it + 1 == max_iter);
+        lap(5);
         for (int t = blockIdx.x; t < d.nst; t += G) {
             if (check) stream_tile<T, true>(d, t, sv, sred);
             else stream_tile<T, false>(d, t, sv, sred);
         }
+        lap(0);
         if (!grid_sync(d.bar, d.abort, G)) return;
+        lap(1);
         for (int t = blockIdx.x; t < d.nlt; t += G) {
             if (check) link_tile<T, kCheck>(d, t, sv, sred);
             else if (save) link_tile<T, kSave>(d, t, sv, sred);
             else link_tile<T, kPlain>(d, t, sv, sred);
         }
+        lap(2);
         if (!grid_sync(d.bar, d.abort, G)) return;
+        lap(3);
         if (!check) continue;
         // finalize: one workgroup per instance, partials in tile order
         const long long delta = it - last_check;
@@ -200,12 +215,17 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
             __syncthreads();
         }
         if (!grid_sync(d.bar, d.abort, G)) return;
+        lap(4);
         int active = 0;
-        for (int i = 0; i < d.B; ++i) active += d.ictl[i].done ? 0 : 1;
-        if (active == 0) return;   // every workgroup sees the same flags
-        if (adapt > 0) {
-            // u <- (rho_old / rho_new) u where this check changed rho (eq. (18));
-            // finalize leaves ratio = 1 otherwise
+        bool rescale = false;
+        for (int i = 0; i < d.B; ++i) {
+            active += d.ictl[i].done ? 0 : 1;
+            rescale |= d.ictl[i].ratio != 1.0;
+        }
+        if (active == 0) break;   // every workgroup sees the same flags
+        // where this check changed rho: u <- (rho_old / rho_new) u (eq. (18));
+        // finalize leaves ratio = 1 otherwise
+        if (adapt > 0 && rescale) {
             for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.g.m; l += G * blockDim.x) {
                 const double r = d.ictl[find_instance(d.link_off, d.B, l)].ratio;
                 if (r != 1.0) {
@@ -217,6 +237,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
             if (!grid_sync(d.bar, d.abort, G)) return;
         }
     }
+    lap(5);
+    if (d.prof && threadIdx.x == 0)
+        for (int k = 0; k < kBatchPhases; ++k) d.prof[(size_t)blockIdx.x * kBatchPhases + k] = ph[k];
 }
 
 }  // namespace
@@ -290,7 +313,7 @@ struct BatchSizes {
 struct BatchLayout {
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
     size_t link_off, stream_off, lo, hi, ictl, hist, st_seg, st_inst, lt_seg, lt_inst;
-    size_t inst_st, inst_lt, st_part, lt_part, bar, util, sperm, total;
+    size_t inst_st, inst_lt, st_part, lt_part, bar, util, sperm, prof, total;
     long long nst_max, nlt_max;
 };
 
@@ -337,6 +360,7 @@ BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap)
     L.bar = take(16);
     L.util = take(N);
     L.sperm = take(N * 4);
+    L.prof = take((size_t)kBatchMaxGrid * kBatchPhases * 8);
     L.total = off;
     return L;
 }
@@ -436,6 +460,7 @@ struct pmp_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_iters = -1;
+    bool profile = false;
 };
 
 namespace {
@@ -562,6 +587,7 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     d.lt_part = (double *)(ws + L.lt_part);
     d.bar = (unsigned *)(ws + L.bar);
     d.abort = (int *)(ws + L.bar + 8);
+    d.prof = opt->profile ? (unsigned long long *)(ws + L.prof) : nullptr;
     BATCH_TRY(hipMemcpyAsync((void *)g.row_ptr, row_ptr.data(), row_ptr.size() * 4, hipMemcpyHostToDevice, s));
     if (E) BATCH_TRY(hipMemcpyAsync((void *)g.col_idx, col_idx.data(), (size_t)E * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)g.c, c.data(), c.size() * sizeof(T), hipMemcpyHostToDevice, s));
@@ -602,12 +628,15 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     BATCH_TRY(hipMemcpyAsync((void *)d.lt_inst, lt_inst.data(), lt_inst.size() * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.inst_st, inst_st.data(), inst_st.size() * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.inst_lt, inst_lt.data(), inst_lt.size() * 4, hipMemcpyHostToDevice, s));
+
     pmp_status st = batch_init_ctl<T>(b);
     if (st != PMP_OK) return st;
     int dev = 0;
     BATCH_TRY(hipGetDevice(&dev));
     b->grid = batch_grid_size<T>(dev, opt->wg_per_cu);
     if (b->grid < 1) return set_error(PMP_ERR_HIP, "occupancy query for the batch kernel failed");
+    if (b->grid > kBatchMaxGrid) b->grid = kBatchMaxGrid;
+    b->profile = opt->profile != 0;
     BATCH_TRY(hipStreamSynchronize(s));
     return PMP_OK;
 }
@@ -691,6 +720,7 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     o->tile_cap[2] = 4096;
     o->reorder_streams = 1;
     o->wg_per_cu = 2;
+    o->profile = 0;
     return PMP_OK;
 }
 
@@ -800,6 +830,25 @@ pmp_status pmp_batch_reset(pmp_batch *b)
     if (st != PMP_OK) return st;
     BATCH_TRY(hipGetLastError());
     BATCH_TRY(hipStreamSynchronize(b->stream));
+    return PMP_OK;
+}
+
+pmp_status pmp_batch_profile(pmp_batch *b, double *ms)
+{
+    if (!b || !ms) return set_error(PMP_ERR_INVALID, "NULL argument");
+    if (!b->profile) return set_error(PMP_ERR_STATE, "the batch was set up without profile = 1");
+    const unsigned long long *dp = b->dtype == PMP_F32 ? b->bf.prof : b->bd.prof;
+    std::vector<unsigned long long> h((size_t)b->grid * kBatchPhases);
+    BATCH_TRY(hipMemcpy(h.data(), dp, h.size() * 8, hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    BATCH_TRY(hipGetDevice(&dev));
+    BATCH_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return set_error(PMP_ERR_HIP, "wall clock rate unknown");
+    for (int k = 0; k < kBatchPhases; ++k) {
+        double sum = 0.0;
+        for (int g = 0; g < b->grid; ++g) sum += (double)h[(size_t)g * kBatchPhases + k];
+        ms[k] = sum / b->grid / khz;   // ticks / kHz = ms
+    }
     return PMP_OK;
 }
 

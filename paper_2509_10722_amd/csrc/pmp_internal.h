@@ -265,7 +265,15 @@ struct BDev {
     double *lt_part;           // [2 nlt]
     unsigned *bar;             // [2] grid barrier: arrivals, generation
     int *abort;                // set when a barrier wait exceeds its bound
+    unsigned long long *prof;  // [grid * kBatchPhases] phase clocks, or NULL
 };
+
+// Phases of the batch kernel timed with pmp_batch_options.profile: stream
+// tiles, wait at the barrier after them, link tiles, wait after them,
+// finalize with its barrier, rescale with its barrier.
+constexpr int kBatchPhases = 6;
+constexpr int kBatchMaxGrid = 4096;   // persistent workgroups at most (8 per CU)
+
 
 template <typename T>
 void launch_batch(const BDev<T> &d, int grid, int max_iter, int check_every, int adapt_every,

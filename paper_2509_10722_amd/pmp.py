@@ -424,7 +424,8 @@ def pmp_objective(c, w, solver, K, s=25):
 
 class pmp_batch_options(ctypes.Structure):
     _fields_ = [("class_m", ctypes.c_int32 * 2), ("tile_cap", ctypes.c_int32 * 3),
-                ("reorder_streams", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+                ("reorder_streams", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
 
 
 _BATCH_SIGNATURES = {
@@ -438,6 +439,7 @@ _BATCH_SIGNATURES = {
     "pmp_batch_solve": [_P, ctypes.c_int32, ctypes.POINTER(pmp_result)],
     "pmp_batch_get_solution": [_P, ctypes.c_int32, _P, _P, _P],
     "pmp_batch_reset": [_P],
+    "pmp_batch_profile": [_P, _P],
     "pmp_batch_destroy": [_P],
 }
 _SIGNATURES.update(_BATCH_SIGNATURES)
@@ -454,8 +456,9 @@ def batch_options_default(**caps) -> pmp_batch_options:
             o.class_m[i] = int(v)
     if "reorder_streams" in caps:
         o.reorder_streams = int(caps["reorder_streams"])
-    if "wg_per_cu" in caps:
-        o.wg_per_cu = int(caps["wg_per_cu"])
+    for key in ("wg_per_cu", "profile"):
+        if key in caps:
+            setattr(o, key, int(caps[key]))
     return o
 
 
@@ -519,6 +522,14 @@ class BatchSolver:
         _check(self.lib.pmp_batch_get_solution(self.handle, int(k), x.data_ptr(), lam.data_ptr(),
                                                slack.data_ptr()), "pmp_batch_get_solution")
         return x[:n], lam, slack
+
+    def profile(self):
+        """Per-phase times (ms, averaged over workgroups) of the last solve's
+        kernel; needs options.profile = 1."""
+        ms = np.zeros(6)
+        _check(self.lib.pmp_batch_profile(self.handle, ms.ctypes.data), "pmp_batch_profile")
+        return dict(zip(("stream_tiles", "stream_barrier", "link_tiles", "link_barrier",
+                         "finalize", "rescale"), ms.tolist()))
 
     def reset(self):
         _check(self.lib.pmp_batch_reset(self.handle), "pmp_batch_reset")

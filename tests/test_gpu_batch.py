@@ -123,3 +123,52 @@ def test_batch_with_alpha2_instance():
         xb, lb, _ = b.solution(k)
         assert close(host(xb), o["x"], 64) and close(host(lb), o["lam"], 64)
     b.close()
+
+
+def test_profile_phases_add_up():
+    """The kernel's phase clocks (pmp_batch_profile) add up to about the
+    duration of the solve, and profiling changes no result."""
+    import time
+    insts = [i.rounded(np.float32) for i in _small_batch(count=8, scale=0.05, seed=5)]
+    outs = []
+    for profile in (0, 1):
+        b = BatchSolver(insts, dtype=torch.float32,
+                        options=batch_options_default(profile=profile))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = b.solve(400)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        outs.append(([r["iterations"] for r in res],
+                     [tuple(host(t) for t in b.solution(k)) for k in range(len(insts))]))
+        if profile:
+            ph = b.profile()
+            total = sum(ph.values())
+            print(f"phases {ph}, sum {total:.2f} ms, solve {dt * 1e3:.2f} ms", flush=True)
+            assert all(v >= 0.0 for v in ph.values())
+            assert 0.5 * dt * 1e3 <= total <= 1.05 * dt * 1e3
+        b.close()
+    assert outs[0][0] == outs[1][0]
+    for (x0, l0, s0), (x1, l1, s1) in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(x0, x1) and np.array_equal(l0, l1) and np.array_equal(s0, s1)
+
+
+def test_batch_results_independent_of_instance_order():
+    """Stress: the same instances in a shuffled order give each instance the
+    same iterations and iterates bit for bit (every sum stays inside its
+    instance and tile)."""
+    insts = [i.rounded(np.float32) for i in _small_batch(count=10, scale=0.02, seed=9)]
+    perm = np.random.default_rng(1).permutation(len(insts))
+    runs = []
+    for order in (np.arange(len(insts)), perm):
+        b = BatchSolver([insts[k] for k in order], dtype=torch.float32)
+        res = b.solve(20000)
+        got = {}
+        for pos, k in enumerate(order):
+            x, lam, _ = b.solution(pos)
+            got[int(k)] = (res[pos]["iterations"], host(x), host(lam))
+        b.close()
+        runs.append(got)
+    for k in range(len(insts)):
+        a, c = runs[0][k], runs[1][k]
+        assert a[0] == c[0] and np.array_equal(a[1], c[1]) and np.array_equal(a[2], c[2])
