@@ -245,7 +245,8 @@ def bench_warmstart(args, log):
             d[f"speedup_{mode}"] = round(tc / tw, 3)
         return d
 
-    base = Solver(inst, dtype=torch.float32, max_iter=args.tol_max_iter)
+    rule = rule_params(args)
+    base = Solver(inst, dtype=torch.float32, max_iter=args.tol_max_iter, **rule)
     r0, t_base = timed_solve(base)
     log(f"[bench] base solve: {r0['iterations']} it, {t_base:.3f} s")
     st0 = base.get_state()
@@ -257,7 +258,7 @@ def bench_warmstart(args, log):
     warm["primal"] = timed_solve(base)
     deg = instances.Instance(inst.name, inst.m, inst.n, inst.row_ptr, inst.col_idx,
                              c_new.astype(np.float64), inst.w, inst.utility, inst.lo, inst.hi)
-    cold = Solver(deg, dtype=torch.float32, max_iter=args.tol_max_iter)
+    cold = Solver(deg, dtype=torch.float32, max_iter=args.tol_max_iter, **rule)
     rc, tc = timed_solve(cold)
     cold.close()
     out["degradation"] = summary(rc, tc, warm)
@@ -279,7 +280,7 @@ def bench_warmstart(args, log):
     pw.set_state(primal_only(pw, stp))
     warm["primal"] = timed_solve(pw)
     pw.close()
-    cold = Solver(pr, dtype=torch.float32, max_iter=args.tol_max_iter)
+    cold = Solver(pr, dtype=torch.float32, max_iter=args.tol_max_iter, **rule)
     rc, tc = timed_solve(cold)
     cold.close()
     out["failure"] = {"links_failed": int(failed.sum()), "m_pruned": pr.m, "n_pruned": pr.n,
@@ -291,9 +292,17 @@ def bench_warmstart(args, log):
     line = {"metric": "warm-start re-solve speedup to 1e-4 (Section V-D)",
             "value": out["degradation"]["speedup_full"], "unit": "x", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": f"{args.config} (m={inst.m}, n={inst.n}, nnz={inst.nnz})"},
+            "config": {"workload": f"{args.config} (m={inst.m}, n={inst.n}, nnz={inst.nnz})",
+                       "stop_rule": args.rule, **rule},
             **out}
     print(json.dumps(line), flush=True)
+
+
+def rule_params(args):
+    """--rule abs: Section III-F's absolute rule, eps_abs = 1e-4; rel: its
+    relative form, eps_rel = 1e-4 of max(||p||, ||z||) and ||rho u||."""
+    return ({"eps_abs": 1e-4, "eps_rel": 0.0} if args.rule == "abs"
+            else {"eps_abs": 0.0, "eps_rel": 1e-4})
 
 
 def bench_congested(args, log):
@@ -311,7 +320,7 @@ def bench_congested(args, log):
     chunk = 2000
     for name, inst in (("uncongested", base), ("congested", cong)):
         inst = inst.rounded(np.float32)
-        s = Solver(inst, dtype=torch.float32, max_iter=chunk)
+        s = Solver(inst, dtype=torch.float32, max_iter=chunk, **rule_params(args))
         s.iterate(20)
         s.reset()
         # solved in chunks of `chunk` iterations (one progress line each), at
@@ -341,7 +350,8 @@ def bench_congested(args, log):
             "unit": "iterations", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": f"{args.config} (m={base.m}, n={base.n}) with 0.1% of links "
-                                   f"on 10% of streams"}, **out}
+                                   f"on 10% of streams", "stop_rule": args.rule,
+                       **rule_params(args)}, **out}
     print(json.dumps(line), flush=True)
 
 
@@ -422,6 +432,9 @@ def main():
                     help="plain: the large workload (the default line); batched / adjoint: "
                          "the two training-system patterns, one JSON line each")
     ap.add_argument("--tune", action="store_true", help="batched: run the tile autotuner first")
+    ap.add_argument("--rule", default="abs", choices=["abs", "rel"],
+                    help="warmstart / congested: stop rule (abs: eps_abs = 1e-4; rel: "
+                         "eps_rel = 1e-4)")
     ap.add_argument("--batch-only", action="store_true",
                     help="batched: one warm-up and one timed solve only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",

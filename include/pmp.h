@@ -98,7 +98,14 @@ typedef struct {
  *   alpha        over-relaxation in (0, 2) (the paper uses 1.6)
  *   mu, gamma    residual-balancing thresholds (> 1; the paper uses 2, 1.1)
  *   eps_abs      absolute tolerance; stop when ||r||, ||s|| < eps_abs sqrt(J),
- *                J = nnz + m terminals
+ *                J = nnz + m terminals (Section III-F)
+ *   eps_rel      relative tolerance (>= 0, default 0): with eps_rel > 0 the
+ *                rule becomes ||r|| < eps_abs sqrt(J) + eps_rel max(||p||, ||z||)
+ *                and ||s|| < eps_abs sqrt(J) + eps_rel ||rho u||, the
+ *                relative form of the ADMM stopping rule that Section III-F
+ *                builds on (norms over all J terminals); each check then
+ *                adds one pass over the n- and m-vectors.  Batched solves
+ *                take the absolute rule only.
  *   adapt_every  rho balancing period in iterations (0 = fixed rho); must be
  *                a multiple of check_every
  *   check_every  residual / stop-test period of pmp_solve (>= 1)
@@ -120,6 +127,7 @@ typedef struct {
     double rho0, alpha, mu, gamma, eps_abs;
     int32_t adapt_every, check_every, max_iter;
     int32_t layout;
+    double eps_rel;
 } pmp_params;
 
 typedef struct {
@@ -240,7 +248,7 @@ pmp_status pmp_get_path_prices(pmp_handle *h, void *pi);
 pmp_status pmp_device_views(pmp_handle *h, void **x, void **u, void **a, void **b,
                             void **zs, void **v);
 
-/* Change eps_abs, mu, gamma and max_iter of an existing handle (alpha,
+/* Change eps_abs, eps_rel, mu, gamma and max_iter of an existing handle (alpha,
  * check_every and adapt_every are fixed at setup: PMP_ERR_INVALID if they
  * differ).  Synchronises the handle's stream. */
 pmp_status pmp_update_params(pmp_handle *h, const pmp_params *params);

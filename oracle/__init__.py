@@ -62,7 +62,7 @@ def _load():
         lib = ctypes.CDLL(build())
         lib.orc_run.restype = ctypes.c_int
         lib.orc_run.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)] + \
-            [ctypes.c_void_p] * 13 + [ctypes.POINTER(_Result)]
+            [ctypes.c_void_p] * 15 + [ctypes.POINTER(_Result)]
         for name in ("orc_prox_log", "orc_prox_linear", "orc_prox_alpha2"):
             f = getattr(lib, name)
             f.restype = ctypes.c_double
@@ -96,14 +96,16 @@ def prox_slack(zeta, c):
 
 def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
         adapt_every=50, check_every=10, stop=False, threads=0, history=False,
-        branches=False):
+        branches=False, state=None, keep_state=False):
     """Run the literal PMP on `inst` for `iters` iterations (or until the stop
     rule fires, when `stop`).  Returns a dict with x, lam (= rho u), slack,
     iterations, r_norm, s_norm, eps_tol, rho, converged, zsum_worst, with
     `history` per-iteration hist_r / hist_s / hist_rho and the norms
     hist_pnorm / hist_znorm / hist_unorm of p, z and rho u, and with
     `branches` the digest of every prox branch taken (clip of each rate,
-    slack projection of each link) over the run."""
+    slack projection of each link) over the run.  `state` (from an earlier
+    run with keep_state=True, same R) starts from that iterate and its rho:
+    a warm start; keep_state=True returns the final iterate as "state"."""
     lib = _load()
     row_ptr = np.ascontiguousarray(inst.row_ptr, dtype=np.int32)
     col_idx = np.ascontiguousarray(inst.col_idx, dtype=np.int32)
@@ -114,6 +116,13 @@ def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
                     _ptr(c), _ptr(w), _ptr(util), float(inst.lo), float(inst.hi))
     prm = _Params(rho0, alpha, mu, gamma, eps_abs, adapt_every, check_every,
                   int(iters), int(bool(stop)), int(threads))
+    J = int(row_ptr[-1]) + inst.m
+    st_in = None
+    if state is not None:
+        st_in = np.ascontiguousarray(state, dtype=np.float64)
+        if st_in.size != 3 * J + inst.m + 1:
+            raise ValueError("state does not match this pattern")
+    st_out = np.zeros(3 * J + inst.m + 1) if keep_state else None
     x = np.zeros(inst.n)
     lam = np.zeros(inst.m)
     slack = np.zeros(inst.m)
@@ -129,7 +138,8 @@ def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
     rc = lib.orc_run(ctypes.byref(prob), ctypes.byref(prm), _ptr(x), _ptr(lam),
                      _ptr(slack), _ptr(hr), _ptr(hs), _ptr(hrho), _ptr(hpn), _ptr(hzn),
                      _ptr(hun), vp(zw), vp(secs),
-                     vp(nthr), vp(dig) if branches else None, ctypes.byref(res))
+                     vp(nthr), vp(dig) if branches else None, _ptr(st_in), _ptr(st_out),
+                     ctypes.byref(res))
     if rc != 0:
         raise RuntimeError(f"orc_run failed with code {rc}")
     out = {"x": x, "lam": lam, "slack": slack, "iterations": int(res.iterations),
@@ -138,6 +148,8 @@ def run(inst, iters, rho0=1.0, alpha=1.6, mu=2.0, gamma=1.1, eps_abs=1e-4,
            "loop_seconds": secs.value, "threads": int(nthr.value)}
     if branches:
         out["branch_digest"] = int(dig.value)
+    if keep_state:
+        out["state"] = st_out
     if history:
         k = int(res.iterations)
         out.update(hist_r=hr[:k], hist_s=hs[:k], hist_rho=hrho[:k], hist_pnorm=hpn[:k],

@@ -214,6 +214,12 @@ static void free_terminals(terminals *T)
  *               digests are equal took the same branches throughout, so the
  *               map from the data to x^K is smooth between them (used to drop
  *               finite-difference pairs that straddle a kink).
+ *   state_in, state_out [3J + m + 1]: the iterate z[J], u[J], p[J] (the last
+ *               iteration's flows, for the next dual residual), pbar[m] and
+ *               rho.  With state_in the run starts from that iterate and its
+ *               rho (rho0 is ignored): a warm start, for instance after the
+ *               capacities changed (Section V-D); state_out receives the
+ *               final iterate in the same layout.
  * Returns 0 on success, -1 on allocation failure, -2 on invalid parameters.
  */
 int orc_run(const orc_problem *P, const orc_params *prm,
@@ -221,7 +227,8 @@ int orc_run(const orc_problem *P, const orc_params *prm,
             double *hist_r, double *hist_s, double *hist_rho,
             double *hist_pn, double *hist_zn, double *hist_un,
             double *zsum_worst, double *loop_seconds, int32_t *threads_used,
-            uint64_t *branch_digest, orc_result *res)
+            uint64_t *branch_digest, const double *state_in, double *state_out,
+            orc_result *res)
 {
     if (prm->max_iter < 0 || prm->rho0 <= 0.0) return -2;
     if (prm->stop && prm->check_every <= 0) return -2;
@@ -257,6 +264,14 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     const double alpha = prm->alpha;
     const double eps_tol = prm->eps_abs * sqrt((double)J);
     double rho = prm->rho0;
+    if (state_in) {
+        memcpy(z, state_in, (size_t)J * sizeof(double));
+        memcpy(u, state_in + J, (size_t)J * sizeof(double));
+        memcpy(p_prev, state_in + 2 * J, (size_t)J * sizeof(double));
+        memcpy(pbar_prev, state_in + 3 * J, (size_t)m * sizeof(double));
+        rho = state_in[3 * J + m];
+        if (!(rho > 0.0)) rho = prm->rho0;
+    }
     double r_norm = 0.0, s_norm = 0.0, zsum_max = 0.0;
     int converged = 0;
     int64_t k;
@@ -383,6 +398,13 @@ int orc_run(const orc_problem *P, const orc_params *prm,
     if (slack) for (int64_t l = 0; l < m; ++l) slack[l] = p[nnz + l] + P->c[l];
     if (zsum_worst) *zsum_worst = zsum_max;
     if (branch_digest) *branch_digest = digest;
+    if (state_out) {
+        memcpy(state_out, z, (size_t)J * sizeof(double));
+        memcpy(state_out + J, u, (size_t)J * sizeof(double));
+        memcpy(state_out + 2 * J, p_prev, (size_t)J * sizeof(double));
+        memcpy(state_out + 3 * J, pbar_prev, (size_t)m * sizeof(double));
+        state_out[3 * J + m] = rho;
+    }
     if (res) {
         res->iterations = k;
         res->r_norm = r_norm;

@@ -44,7 +44,8 @@ struct Layout {
     bool binned;
     BinnedPlan bp;
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
-    size_t sblk, lblk, spart, lpart, ctl, hist, util, lck_beg, lck_end, lr_row, lr_ck, rpart, total;
+    size_t sblk, lblk, spart, lpart, ctl, hist, util, lck_beg, lck_end, lr_row, lr_ck, rpart, npart,
+        total;
     int nsb_max, nlb_max, nlc_max, nlr_max;
 };
 
@@ -124,6 +125,7 @@ Layout plan(int m, int n, long long nnz, size_t sz, int layout)
     L.lr_row = take((size_t)L.nlr_max * 4);
     L.lr_ck = take(((size_t)L.nlr_max + 1) * 4);
     L.rpart = take((size_t)L.nlc_max * 8);
+    L.npart = take((size_t)kNormBlocks * 5 * 8);
     L.ctl = take(sizeof(Ctl));
     L.hist = take(sizeof(HistEntry) * kHist);
     L.util = take((size_t)n);
@@ -236,6 +238,8 @@ pmp_status check_params(const pmp_params *p)
     if (!(p->alpha > 0.0 && p->alpha < 2.0)) return fail(PMP_ERR_INVALID, "alpha must be in (0, 2)");
     if (!(p->mu > 1.0) || !(p->gamma > 1.0)) return fail(PMP_ERR_INVALID, "mu and gamma must be > 1");
     if (!(p->eps_abs >= 0.0)) return fail(PMP_ERR_INVALID, "eps_abs must be >= 0");
+    if (!(p->eps_rel >= 0.0) || !std::isfinite(p->eps_rel))
+        return fail(PMP_ERR_INVALID, "eps_rel must be finite and >= 0");
     if (p->check_every < 1) return fail(PMP_ERR_INVALID, "check_every must be >= 1");
     if (p->adapt_every < 0 || (p->adapt_every > 0 && p->adapt_every % p->check_every != 0))
         return fail(PMP_ERR_INVALID, "adapt_every must be 0 or a multiple of check_every");
@@ -299,6 +303,7 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     d.lr_row = (int *)(ws + L.lr_row);
     d.lr_ck = (int *)(ws + L.lr_ck);
     d.rpart = (double *)(ws + L.rpart);
+    d.npart = (double *)(ws + L.npart);
     d.ctl = (Ctl *)(ws + L.ctl);
     d.hist = (HistEntry *)(ws + L.hist);
     d.lo = p->lo;
@@ -307,7 +312,8 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
     h->ctl = d.ctl;
 
     const double J = (double)nnz + (double)m;
-    launch_ctl_init(d.ctl, h->prm.rho0, h->prm.eps_abs * std::sqrt(J), h->prm.mu, h->prm.gamma,
+    launch_ctl_init(d.ctl, h->prm.rho0, h->prm.eps_abs * std::sqrt(J), h->prm.eps_rel, h->prm.mu,
+                    h->prm.gamma,
                     h->prm.adapt_every, s);
 
     // Inputs into the workspace.
@@ -936,6 +942,7 @@ pmp_status pmp_params_default(pmp_params *p)
     p->check_every = 10;
     p->max_iter = 100000;
     p->layout = PMP_LAYOUT_AUTO;
+    p->eps_rel = 0.0;
     return PMP_OK;
 }
 
@@ -1164,7 +1171,7 @@ pmp_status pmp_set_state(pmp_handle *h, const void *state)
     Ctl c;
     HIP_TRY(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    launch_ctl_init(h->ctl, rho, c.eps_tol, c.mu, c.gamma, c.adapt_every, s);
+    launch_ctl_init(h->ctl, rho, c.eps_tol, c.eps_rel, c.mu, c.gamma, c.adapt_every, s);
     HIP_TRY(hipMemcpyAsync(&h->ctl->iter, &it, 8, hipMemcpyHostToDevice, s));
     if (h->dtype == PMP_F32) {
         launch_refresh_v<float>(h->df, s);
@@ -1188,11 +1195,13 @@ pmp_status pmp_update_params(pmp_handle *h, const pmp_params *params)
         params->adapt_every != h->prm.adapt_every || params->layout != h->prm.layout)
         return fail(PMP_ERR_INVALID, "alpha, check_every, adapt_every and layout are fixed at setup");
     h->prm.eps_abs = params->eps_abs;
+    h->prm.eps_rel = params->eps_rel;
     h->prm.mu = params->mu;
     h->prm.gamma = params->gamma;
     h->prm.max_iter = params->max_iter;
     const double J = (double)h->nnz + (double)h->m;
-    launch_ctl_set_tolerances(h->ctl, params->eps_abs * std::sqrt(J), params->mu, params->gamma,
+    launch_ctl_set_tolerances(h->ctl, params->eps_abs * std::sqrt(J), params->eps_rel, params->mu,
+                              params->gamma,
                               h->stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(h->stream));

@@ -741,6 +741,8 @@ static pmp_status check_batch_args(int32_t count, const pmp_problem *pr, const p
         return set_error(PMP_ERR_INVALID, "adapt_every must be 0 or a multiple of check_every");
     if (!(prm->rho0 > 0.0) || !(prm->alpha > 0.0 && prm->alpha < 2.0) || !(prm->mu > 1.0) || !(prm->gamma > 1.0))
         return set_error(PMP_ERR_INVALID, "rho0 > 0, alpha in (0, 2), mu > 1 and gamma > 1 required");
+    if (prm->eps_rel != 0.0)
+        return set_error(PMP_ERR_INVALID, "batched solves take the absolute stop rule (eps_rel = 0)");
     return PMP_OK;
 }
 

@@ -285,15 +285,27 @@ __device__ __forceinline__ void adj_stream_step(const Dev<T> &d, const AdjDev &a
 // ---- residual reduction, stop rule and rho balancing ---------------------
 
 // Thread 0 of the check-finalize kernel: residual norms (Section III-F), the
-// stop rule, and residual balancing of rho (Section III-G).
+// stop rule, and residual balancing of rho (Section III-G).  nrm (or NULL):
+// sums of squares of p, z and u over all terminals, for the relative part
+// of the stop rule: ||r|| < eps_abs sqrt(J) + eps_rel max(||p||, ||z||) and
+// ||s|| < eps_abs sqrt(J) + eps_rel ||rho u||.
 template <typename T>
-__device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, double ss)
+__device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, double ss,
+                         const double *nrm = nullptr)
 {
     Ctl *c = d.ctl;
     const double rho = c->rho;
     const long long it = c->iter + delta;
     const double r = sqrt(sr);
     const double s = rho * sqrt(ss > 0.0 ? ss : (ss == ss ? 0.0 : ss));   // keeps a NaN
+    double tol_r = c->eps_tol, tol_s = c->eps_tol;
+    if (nrm && c->eps_rel > 0.0) {
+        c->p_norm = sqrt(fmax(nrm[0], 0.0));
+        c->z_norm = sqrt(fmax(nrm[1], 0.0));
+        c->u_norm = rho * sqrt(fmax(nrm[2], 0.0));
+        tol_r += c->eps_rel * fmax(c->p_norm, c->z_norm);
+        tol_s += c->eps_rel * c->u_norm;
+    }
     c->iter = it;
     c->r_norm = r;
     c->s_norm = s;
@@ -307,7 +319,7 @@ __device__ void finalize(const Dev<T> &d, long long delta, int stop, double sr, 
     if (!isfinite(r) || !isfinite(s)) {
         c->status = PMP_ERR_NUMERIC;
         c->done = 1;
-    } else if (stop && r < c->eps_tol && s < c->eps_tol) {
+    } else if (stop && r < tol_r && s < tol_s) {
         c->status = PMP_OK;
         c->done = 1;
     } else if (c->adapt_every > 0 && it % c->adapt_every == 0) {

@@ -24,6 +24,8 @@ constexpr int kLongChunk = 8192;
 constexpr int kHist = 4096;
 // Threads of the kernel that reduces the residual partials of a check.
 constexpr int kFinThreads = 1024;
+// Workgroups of the norm pass of a check with a relative stop rule.
+constexpr int kNormBlocks = 256;
 
 // Device-resident control block.  Kernels read rho and the done flag from
 // here, so a captured graph stays valid while rho changes (Section III-G
@@ -34,6 +36,8 @@ struct Ctl {
     double r_norm;         // ||r|| at the last check
     double s_norm;         // ||s|| at the last check
     double eps_tol;        // eps_abs sqrt(J)
+    double eps_rel;        // relative part of the stop rule (0 = absolute only)
+    double p_norm, z_norm, u_norm;   // ||p||, ||z||, ||rho u|| at the last check (eps_rel > 0)
     double mu, gamma;      // balancing thresholds
     long long iter;        // iterations completed at the last check
     long long nhist;       // checks recorded in the history ring
@@ -91,6 +95,7 @@ struct Dev {
     const int *lck_beg, *lck_end;   // [nlc] nonzero range of each chunk
     const int *lr_row, *lr_ck;      // [nlr], [nlr + 1] long rows and their chunks
     double *rpart;                  // [nlc] chunk sums
+    double *npart;                  // [kNormBlocks * 5] partials of the norms of a check
     double lo, hi, alpha;
     // Long rows (more than kCap nonzeros, congested links) of FP32 problems
     // with a finite box are summed in fixed point: each rate x becomes the
@@ -311,12 +316,13 @@ size_t transpose_scratch_ints(int n);
 void launch_transpose(const int *row_ptr, const int *col_idx, int m, int n, long long nnz,
                       int *col_ptr, int *row_idx, int *tmp, hipStream_t s);
 void launch_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl, hipStream_t s);
-void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gamma,
-                     int adapt_every, hipStream_t s);
+void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double eps_rel, double mu,
+                     double gamma, int adapt_every, hipStream_t s);
 void launch_ctl_clear_done(Ctl *ctl, hipStream_t s);
 // Count k iterations run without a check (ctl->iter += k).
 void launch_ctl_advance(Ctl *ctl, long long k, hipStream_t s);
-void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double mu, double gamma, hipStream_t s);
+void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double eps_rel, double mu, double gamma,
+                               hipStream_t s);
 void launch_fill_int(int *p, int value, size_t count, hipStream_t s);
 
 }  // namespace pmp

@@ -149,7 +149,58 @@ __global__ __launch_bounds__(kFinThreads) void k_check_finalize(Dev<T> d, int ns
     for (int i = threadIdx.x; i < nspart; i += kFinThreads) ss += d.spart[i];
     sr = block_sum_n<kFinThreads>(sr, sred);
     ss = block_sum_n<kFinThreads>(ss, sred);
-    if (threadIdx.x == 0) finalize<T>(d, delta, stop, sr, ss);
+    // norms of p, z, u from the norm pass (relative stop rule only)
+    double nrm[3] = {0.0, 0.0, 0.0};
+    const bool rel = d.ctl->eps_rel > 0.0;
+    if (rel) {
+        double q[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            double acc = 0.0;
+            for (int i = threadIdx.x; i < kNormBlocks; i += kFinThreads) acc += d.npart[5 * i + k];
+            q[k] = block_sum_n<kFinThreads>(acc, sred);
+        }
+        nrm[0] = q[0] + q[2];   // sum_j L x^2 + sum_l ps^2
+        nrm[1] = q[1] + q[3];   // sum_(l,j) (a_j + b_l)^2 + sum_l zs^2
+        nrm[2] = q[4];          // sum_l (d + 1) u^2
+    }
+    if (threadIdx.x == 0) finalize<T>(d, delta, stop, sr, ss, rel ? nrm : nullptr);
+}
+
+// Norms of a check for the relative stop rule, per workgroup (partials in
+// npart, added in a fixed order by k_check_finalize).  In the compact form a
+// traffic terminal (l, j) holds p = x_j and z = a_j + b_l, a slack terminal
+// p = ps_l and z = zs_l, every terminal of link l the dual u_l.  With the
+// link balance (R a)_l = -(d_l b_l + zs_l) (the z-update keeps each link's
+// z summing to zero),
+//   sum over traffic terminals of z^2 = sum_j L_j a_j^2 - sum_l (d_l b_l^2 + 2 b_l zs_l),
+// so no sum over the nonzeros is needed.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rel_norms(Dev<T> d)
+{
+    if (d.ctl->done || !(d.ctl->eps_rel > 0.0)) return;
+    __shared__ double sred[kBlock / 64];
+    double q[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += stride) {
+        const double L = d.rlen ? (double)d.rlen[j] : (double)(d.col_ptr[j + 1] - d.col_ptr[j]);
+        const double x = (double)d.x[j], a = (double)d.a[j];
+        q[0] += L * x * x;
+        q[1] += L * a * a;
+    }
+    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += stride) {
+        const double dg = d.dlen ? (double)d.dlen[l] : (double)(d.row_ptr[l + 1] - d.row_ptr[l]);
+        const double ps = d.ps_prev[l], b = (double)d.b[l], zs = (double)d.zs[l];
+        const double u = (double)d.u[l];
+        q[2] += ps * ps;
+        q[3] += zs * zs - dg * b * b - 2.0 * b * zs;
+        q[4] += (dg + 1.0) * u * u;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double t = block_sum(q[k], sred);
+        if (threadIdx.x == 0) d.npart[5 * blockIdx.x + k] = t;
+    }
 }
 
 // u <- (rho_old / rho_new) u after a balancing step (eq. (18)); v = b - u.
@@ -381,14 +432,16 @@ __global__ void k_fill_int(int *p, int value, size_t count)
         p[i] = value;
 }
 
-__global__ void k_ctl_init(Ctl *c, double rho, double eps_tol, double mu, double gamma,
-                           int adapt_every)
+__global__ void k_ctl_init(Ctl *c, double rho, double eps_tol, double eps_rel, double mu,
+                           double gamma, int adapt_every)
 {
     c->rho = rho;
     c->ratio = 1.0;
     c->r_norm = 0.0;
     c->s_norm = 0.0;
     c->eps_tol = eps_tol;
+    c->eps_rel = eps_rel;
+    c->p_norm = c->z_norm = c->u_norm = 0.0;
     c->mu = mu;
     c->gamma = gamma;
     c->iter = 0;
@@ -400,9 +453,11 @@ __global__ void k_ctl_init(Ctl *c, double rho, double eps_tol, double mu, double
     c->flags = 0u;
 }
 
-__global__ void k_ctl_set_tolerances(Ctl *c, double eps_tol, double mu, double gamma)
+__global__ void k_ctl_set_tolerances(Ctl *c, double eps_tol, double eps_rel, double mu,
+                                     double gamma)
 {
     c->eps_tol = eps_tol;
+    c->eps_rel = eps_rel;
     c->mu = mu;
     c->gamma = gamma;
 }
@@ -513,6 +568,8 @@ template <typename T>
 void launch_check_finalize(const Dev<T> &d, int nspart, int nlpart, long long delta, int stop,
                            hipStream_t s)
 {
+    // the norm pass returns at once unless the stop rule has a relative part
+    hipLaunchKernelGGL((k_rel_norms<T>), dim3(kNormBlocks), dim3(kBlock), 0, s, d);
     hipLaunchKernelGGL((k_check_finalize<T>), dim3(1), dim3(kFinThreads), 0, s, d, nspart, nlpart,
                        delta, stop);
 }
@@ -640,16 +697,18 @@ void launch_check_routes(const int *col_ptr, int n, double hi, Ctl *ctl, hipStre
                        col_ptr, n, hi, ctl);
 }
 
-void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double mu, double gamma,
-                     int adapt_every, hipStream_t s)
+void launch_ctl_init(Ctl *ctl, double rho, double eps_tol, double eps_rel, double mu,
+                     double gamma, int adapt_every, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, ctl, rho, eps_tol, mu, gamma,
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, s, ctl, rho, eps_tol, eps_rel, mu, gamma,
                        adapt_every);
 }
 
-void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double mu, double gamma, hipStream_t s)
+void launch_ctl_set_tolerances(Ctl *ctl, double eps_tol, double eps_rel, double mu, double gamma,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ctl_set_tolerances, dim3(1), dim3(1), 0, s, ctl, eps_tol, mu, gamma);
+    hipLaunchKernelGGL(k_ctl_set_tolerances, dim3(1), dim3(1), 0, s, ctl, eps_tol, eps_rel, mu,
+                       gamma);
 }
 
 void launch_ctl_clear_done(Ctl *ctl, hipStream_t s)

@@ -42,7 +42,7 @@ class pmp_params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("eps_abs", ctypes.c_double), ("adapt_every", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("layout", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("eps_rel", ctypes.c_double)]
 
 
 class pmp_result(ctypes.Structure):

@@ -29,7 +29,7 @@ typedef struct {
 
 int orc_run(const orc_problem *, const orc_params *, double *, double *, double *, double *,
             double *, double *, double *, double *, double *, double *, double *, int32_t *,
-            uint64_t *, orc_result *);
+            uint64_t *, const double *, double *, orc_result *);
 double orc_prox_log(double, int64_t, double, double, double, double);
 double orc_prox_linear(double, int64_t, double, double, double, double);
 double orc_prox_alpha2(double, int64_t, double, double, double, double);
@@ -87,7 +87,7 @@ static void run_case(int m, int n, int busy, int util_mode)
         int32_t thr = 0;
         orc_result res;
         REQUIRE(orc_run(&P, &prm, x, lam, sl, hr, hs, hp, hn, hn + K, hn + 2 * K, &zw, &secs, &thr,
-                        &dig, &res) == 0);
+                        &dig, NULL, NULL, &res) == 0);
         REQUIRE(res.iterations >= 1 && res.iterations <= K);
         for (int j = 0; j < n; ++j) REQUIRE(isfinite(x[j]) && x[j] >= 0.0 && x[j] <= 10.0);
         REQUIRE(x[n - 1] == 10.0);      /* empty route: the upper bound */
@@ -97,7 +97,7 @@ static void run_case(int m, int n, int busy, int util_mode)
     /* NULL outputs are allowed */
     orc_params prm = {1.0, 1.6, 2.0, 1.1, 1e-4, 50, 10, 20, 0, 0};
     orc_result res;
-    REQUIRE(orc_run(&P, &prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
+    REQUIRE(orc_run(&P, &prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
     free(row_ptr); free(col_idx); free(c); free(w); free(u); free(x); free(lam); free(sl);
     free(hr); free(hs); free(hp); free(hn);
 }
@@ -119,9 +119,9 @@ int main(void)
         orc_problem P = {1, 0, 0, rp, rp, &c1, &c1, NULL, 0.0, 1.0};
         orc_params bad = {0.0, 1.6, 2.0, 1.1, 1e-4, 0, 10, 5, 0, 1};
         orc_result res;
-        REQUIRE(orc_run(&P, &bad, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == -2);
+        REQUIRE(orc_run(&P, &bad, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == -2);
         orc_params ok = {1.0, 1.6, 2.0, 1.1, 1e-4, 0, 10, 5, 0, 1};  /* no streams at all */
-        REQUIRE(orc_run(&P, &ok, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
+        REQUIRE(orc_run(&P, &ok, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &res) == 0);
     }
     for (int mode = 0; mode < 4; ++mode) {
         run_case(40, 60, 1, mode);

@@ -45,7 +45,7 @@ def test_defaults_follow_the_paper():
     from paper_2509_10722_amd import pmp
     p = pmp.params_default()
     assert (p.rho0, p.alpha, p.mu, p.gamma, p.adapt_every) == (1.0, 1.6, 2.0, 1.1, 50)
-    assert p.check_every == 10 and abs(p.eps_abs - 1e-4) < 1e-18
+    assert p.check_every == 10 and abs(p.eps_abs - 1e-4) < 1e-18 and p.eps_rel == 0.0
 
 
 def test_workspace_size_and_shape_errors():
@@ -83,6 +83,7 @@ def test_binned_layout_size_limits():
 
 @pytest.mark.parametrize("field,value,status", [
     ("rho0", 0.0, 1), ("alpha", 2.5, 1), ("mu", 1.0, 1), ("gamma", 0.5, 1),
+    ("eps_rel", -1e-4, 1), ("eps_rel", float("nan"), 1),
     ("check_every", 0, 1), ("adapt_every", 15, 1),
 ])
 def test_setup_rejects_bad_params_without_device_work(field, value, status):

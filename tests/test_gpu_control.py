@@ -169,3 +169,39 @@ def test_nonfinite_iterate_reports_numeric(dtype_name, layout):
     s.reset()
     assert s.solve()["converged"]
     s.close()
+
+
+def _first_check(o, eps_abs, eps_rel, J, ce=10):
+    """The first check iteration at which the oracle's own norms meet
+    ||r|| < eps_abs sqrt(J) + eps_rel max(||p||, ||z||) and
+    ||s|| < eps_abs sqrt(J) + eps_rel ||rho u||."""
+    k = np.arange(ce, len(o["hist_r"]) + 1, ce)
+    tr = eps_abs * np.sqrt(J) + eps_rel * np.maximum(o["hist_pnorm"], o["hist_znorm"])[k - 1]
+    ts = eps_abs * np.sqrt(J) + eps_rel * o["hist_unorm"][k - 1]
+    hit = k[(o["hist_r"][k - 1] < tr) & (o["hist_s"][k - 1] < ts)]
+    return int(hit[0]) if hit.size else None
+
+
+@pytest.mark.parametrize("dtype_name,eps_abs,layout", [
+    ("float64", 0.0, 1), ("float64", 1e-4, 1), ("float64", 0.0, 2), ("float32", 0.0, 1),
+    ("float32", 0.0, 2)])
+def test_relative_stop_rule_matches_oracle(dtype_name, eps_abs, layout):
+    """eps_rel = 1e-4 (the relative form of the ADMM stopping rule that
+    Section III-F builds on): the GPU stops at the check where the oracle's
+    per-iteration norms of p, z and rho u (pinned against a per-terminal
+    restatement) first meet the rule; FP64 exactly, FP32 within two checks."""
+    dtype = getattr(torch, dtype_name)
+    inst = I.tiny() if dtype_name == "float64" else I.tiny().rounded(np.float32)
+    _say(f"relative stop rule, {dtype_name}, eps_abs {eps_abs}, layout {layout}")
+    s = Solver(inst, dtype=dtype, eps_abs=eps_abs, eps_rel=1e-4, layout=layout)
+    res = s.solve()
+    x, _, _ = s.solution()
+    s.close()
+    o = oracle.run(inst, res["iterations"] + 300, history=True)
+    k = _first_check(o, eps_abs, 1e-4, inst.nnz + inst.m)
+    _say(f"  GPU stops at {res['iterations']}, oracle's first check meeting the rule {k}")
+    assert res["converged"] and k is not None
+    if dtype_name == "float64":
+        assert res["iterations"] == k
+    else:
+        assert abs(res["iterations"] - k) <= 20
