@@ -94,6 +94,20 @@ static void run_case(int m, int n, int busy, int util_mode)
         for (int l = 0; l < m; ++l) REQUIRE(isfinite(lam[l]) && isfinite(sl[l]));
         REQUIRE(zw < 1e-9);
     }
+    /* warm start: the saved iterate of one run starts the next */
+    {
+        const long long J = (long long)P.nnz + P.m;
+        double *st = malloc((size_t)(3 * J + P.m + 1) * sizeof(double));
+        double *st2 = malloc((size_t)(3 * J + P.m + 1) * sizeof(double));
+        orc_params prm2 = {1.0, 1.6, 2.0, 1.1, 1e-4, 50, 10, 30, 0, 2};
+        orc_result res2;
+        REQUIRE(orc_run(&P, &prm2, x, lam, sl, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL,
+                        NULL, NULL, st, &res2) == 0);
+        REQUIRE(orc_run(&P, &prm2, x, lam, sl, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL,
+                        NULL, st, st2, &res2) == 0);
+        REQUIRE(st2[3 * J + P.m] > 0.0);
+        free(st); free(st2);
+    }
     /* NULL outputs are allowed */
     orc_params prm = {1.0, 1.6, 2.0, 1.1, 1e-4, 50, 10, 20, 0, 0};
     orc_result res;
