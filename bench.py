@@ -154,6 +154,80 @@ def bench_batched(args, log):
     print(json.dumps(line), flush=True)
 
 
+def bench_batched_congested(args, log):
+    """Pattern 2 under Section V-C's congestion: the 64 transit instances of
+    the batched workload, each with 0.1% of its links added to 10% of its
+    streams (the largest get rows of up to 50,000 nonzeros), iterated a fixed
+    number of times (no stop rule, so every instance does the same work) by
+    one persistent launch: long rows in chunk tiles of heavy_chunk nonzeros
+    against one workgroup per long row, and against one-by-one solves."""
+    import numpy as np
+    import torch
+
+    from paper_2509_10722_amd import autotune, instances
+    from paper_2509_10722_amd.pmp import BatchSolver, Solver
+
+    base = instances.batched(scale=args.scale)
+    insts = [instances.congested(i, seed=100 + k).rounded(np.float32) for k, i in enumerate(base)]
+    del base
+    tot = {"m": sum(i.m for i in insts), "n": sum(i.n for i in insts),
+           "nnz": sum(i.nnz for i in insts),
+           "long_rows": int(sum(int(np.sum(np.diff(i.row_ptr) > autotune.LONG_ROW)) for i in insts)),
+           "longest_row": int(max(int(np.diff(i.row_ptr).max()) for i in insts))}
+    log(f"[bench] congested batch: {len(insts)} instances, {tot}")
+    K = args.steps
+    if args.tune:
+        opts, _ = autotune.tune_batch(insts, dtype=torch.float32, log=log)
+    else:
+        opts = autotune.cached_options(torch)
+    if args.heavy_chunk:
+        opts.heavy_chunk = args.heavy_chunk
+
+    def batched(chunk):
+        opts.heavy_chunk = chunk
+        b = BatchSolver(insts, dtype=torch.float32, options=opts, eps_abs=0.0)
+        b.solve(20)
+        b.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.solve(K)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        x = [b.solution(k)[0].cpu() for k in range(len(insts))]
+        b.close()
+        return t, x
+
+    chunk = int(opts.heavy_chunk)
+    tb, xb = batched(chunk)
+    log(f"[bench] heavy_chunk {chunk}: {K} iterations in {tb:.3f} s")
+    t1, x1 = batched(1 << 20)
+    log(f"[bench] one workgroup per long row: {K} iterations in {t1:.3f} s")
+    same = all(torch.equal(a, c) for a, c in zip(xb, x1))
+    tp = 0.0
+    for inst in insts:
+        s = Solver(inst, dtype=torch.float32, eps_abs=0.0, max_iter=K)
+        s.solve()                       # graph capture
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve()
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t0
+        s.close()
+    log(f"[bench] one by one: {tp:.3f} s")
+    line = {
+        "metric": "batched PMP instance-iterations/sec (64 congested transit instances, fixed K)",
+        "value": round(len(insts) * K / tb, 1), "unit": "instance-iter/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"congested batched transit x{len(insts)}", **tot, "K": K,
+                   "heavy_chunk": chunk},
+        "time_s": round(tb, 4), "row_per_workgroup_time_s": round(t1, 4),
+        "chunking_speedup": round(t1 / tb, 3), "plain_time_s": round(tp, 4),
+        "speedup_vs_plain": round(tp / tb, 3), "iterates_equal_across_chunks": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_adjoint(args, log):
     """Pattern 3: gradient of sum_j w_j log x_j^K (K = 500, checkpoints every
     25) with respect to c and w on the adjoint workload, against K plain
@@ -435,6 +509,10 @@ def main():
     ap.add_argument("--rule", default="abs", choices=["abs", "rel"],
                     help="warmstart / congested: stop rule (abs: eps_abs = 1e-4; rel: "
                          "eps_rel = 1e-4)")
+    ap.add_argument("--congested", action="store_true",
+                    help="batched: congested transit instances (Section V-C), fixed iterations")
+    ap.add_argument("--heavy-chunk", type=int, default=0,
+                    help="batched: nonzeros per chunk of a long link row (0: cached or default)")
     ap.add_argument("--batch-only", action="store_true",
                     help="batched: one warm-up and one timed solve only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -460,7 +538,7 @@ def main():
         sys.exit(1)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     if args.pattern == "batched":
-        return bench_batched(args, log)
+        return bench_batched_congested(args, log) if args.congested else bench_batched(args, log)
     if args.pattern == "adjoint":
         return bench_adjoint(args, log)
     if args.pattern == "warmstart":

@@ -390,17 +390,9 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         // (longest row) x hi x 2^F <= 2^62, every term and every partial sum
         // fits an int64.  A quantum 2^-F above 2^-24 (very large hi x row
         // length) would lose more than FP32 rounding: then FP64 sums are kept.
-        d.fx_shift = 0;
-        d.fx_scale = d.fx_inv = 1.0;
-        if (sizeof(T) == 4 && maxlong > 0 && std::isfinite(p->hi) && p->hi > 0.0) {
-            int F = (int)std::floor(62.0 - std::log2((double)maxlong * p->hi));
-            F = std::min(F, 126);
-            if (F >= 24) {
-                d.fx_shift = F;
-                d.fx_scale = std::ldexp(1.0, F);
-                d.fx_inv = std::ldexp(1.0, -F);
-            }
-        }
+        d.fx_shift = long_row_shift(sizeof(T), maxlong, p->hi);
+        d.fx_scale = std::ldexp(1.0, d.fx_shift);
+        d.fx_inv = std::ldexp(1.0, -d.fx_shift);
         if (d.nlc > L.nlc_max || d.nlr > L.nlr_max)
             return fail(PMP_ERR_SHAPE, "internal: long-row tables exceed their bound");
         if (d.nlc) {

@@ -107,17 +107,84 @@ __device__ void stream_tile(const BDev<T> &d, int tile, T *sv, double *sred)
     __syncthreads();   // sv is reused by the next tile
 }
 
+// Chunk k of the nch chunks of a long link row (a congested link): its sum
+// over heavy_chunk nonzeros (strided over the workgroup, then a fixed tree;
+// in fixed point where the instance's long rows are), published in lt_hsum.
+// The workgroup that makes the row's last arrival adds the row's chunk sums
+// in chunk order and runs the link update; that order and these chunks are
+// those of the single-instance gather layout, so the row comes out the same
+// as there.  Returns (in thread 0) whether this workgroup updated the link.
+template <typename T, int MODE>
+__device__ bool link_chunk(const BDev<T> &d, const Dev<T> &di, int inst, int tile, int k, int nch,
+                           double *sred, double &r2, double &s2)
+{
+    const int l = d.lt_seg[tile];
+    const int rb = di.row_ptr[l], re = di.row_ptr[l + 1];
+    const int cb = rb + k * d.heavy_chunk;
+    const int ce = cb + min(re - cb, d.heavy_chunk);
+    const int fx = d.ifx_shift[inst];
+    long long bits;
+    if (fx) {
+        const double sc = d.ifx_scale[inst];
+        long long acc = 0;
+        for (int e = cb + (int)threadIdx.x; e < ce; e += kBlock)
+            acc += fx_term((double)di.x[ld_stream(di.col_idx + e)], sc);
+        bits = block_sum_ll(acc, sred);
+    } else {
+        double acc = 0.0;
+        for (int e = cb + (int)threadIdx.x; e < ce; e += kBlock)
+            acc += (double)di.x[ld_stream(di.col_idx + e)];
+        bits = __double_as_longlong(block_sum(acc, sred));
+    }
+    bool last = false;
+    if (threadIdx.x == 0) {
+        const int t0 = tile - k;
+        last = true;
+        if (nch > 1) {
+            __hip_atomic_store(&d.lt_hsum[tile], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            last = atomicAdd(&d.lt_hcnt[t0], 1u) == (unsigned)(nch - 1);
+            if (last) __threadfence();
+        }
+        if (last) {
+            double y = 0.0;
+            if (fx) {
+                long long t = 0;
+                for (int q = 0; q < nch; ++q)
+                    t += q == k ? bits
+                                : __hip_atomic_load(&d.lt_hsum[t0 + q], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                y = (double)t * d.ifx_inv[inst];
+            } else {
+                for (int q = 0; q < nch; ++q)
+                    y += __longlong_as_double(q == k ? bits
+                                                     : __hip_atomic_load(&d.lt_hsum[t0 + q], __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT));
+            }
+            // the next iteration's arrivals come after two grid barriers
+            if (nch > 1) __hip_atomic_store(&d.lt_hcnt[t0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            link_update<T, MODE>(di, l, re - rb, y, r2, s2);
+        }
+    }
+    return last;
+}
+
 template <typename T, int MODE>
 __device__ void link_tile(const BDev<T> &d, int tile, T *sx, double *sred)
 {
     const int inst = d.lt_inst[tile];
     if (d.ictl[inst].done) return;
     const Dev<T> di = instance_view(d, inst);
-    const int l0 = d.lt_seg[tile], l1 = d.lt_seg[tile + 1];
-    const int e0 = di.row_ptr[l0];
-    const int cnt = di.row_ptr[l1] - e0;
+    const int2 ck = d.lt_ck[tile];
     double r2 = 0.0, s2 = 0.0;
-    if (cnt <= kCap) {
+    bool last = false;
+    if (ck.y > 0) {
+        last = link_chunk<T, MODE>(d, di, inst, tile, ck.x, ck.y, sred, r2, s2);
+    } else {
+        // at most kCap nonzeros: rows longer than that are chunk tiles
+        const int l0 = d.lt_seg[tile], l1 = d.lt_seg[tile + 1];
+        const int e0 = di.row_ptr[l0];
+        const int cnt = di.row_ptr[l1] - e0;
         gather_stage<T>(di.col_idx + e0, di.x, sx, cnt);
         __syncthreads();
         const int l = l0 + (int)threadIdx.x;
@@ -126,19 +193,27 @@ __device__ void link_tile(const BDev<T> &d, int tile, T *sx, double *sred)
             const double acc = run_sum<T>(sx, b, e);
             link_update<T, MODE>(di, l, e - b, acc, r2, s2);
         }
-    } else {
-        double acc = 0.0;
-        for (int k = threadIdx.x; k < cnt; k += kBlock)
-            acc += (double)di.x[ld_stream(di.col_idx + e0 + k)];
-        acc = block_sum(acc, sred);
-        if (threadIdx.x == 0) link_update<T, MODE>(di, l0, cnt, acc, r2, s2);
     }
     if (MODE == kCheck) {
         r2 = block_sum(r2, sred);
         s2 = block_sum(s2, sred);
         if (threadIdx.x == 0) {
-            d.lt_part[2 * tile] = r2;
-            d.lt_part[2 * tile + 1] = s2;
+            if (ck.y == 0) {
+                d.lt_part[2 * tile] = r2;
+                d.lt_part[2 * tile + 1] = s2;
+            } else {
+                // a long row's norms go to its first chunk tile, whichever
+                // workgroup updated it, so the check adds them in a fixed
+                // order; the other chunk tiles hold zeros
+                if (ck.x > 0) {
+                    d.lt_part[2 * tile] = 0.0;
+                    d.lt_part[2 * tile + 1] = 0.0;
+                }
+                if (last) {
+                    d.lt_part[2 * (tile - ck.x)] = r2;
+                    d.lt_part[2 * (tile - ck.x) + 1] = s2;
+                }
+            }
         }
     }
     __syncthreads();
@@ -171,9 +246,13 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
             tmark = now;
         }
     };
-    // a solve call continues every instance from its current state
+    // a solve call continues every instance from its current state; the
+    // long rows' arrival counters start at zero (a launch that left through
+    // an expired barrier wait may have left counts behind)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.B; i += G * blockDim.x)
         d.ictl[i].done = 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.nlt; t += G * blockDim.x)
+        d.lt_hcnt[t] = 0;
     if (!grid_sync(d.bar, d.abort, G)) return;
     long long last_check = 0;
     for (int it = 1; it <= max_iter; ++it) {
@@ -313,11 +392,12 @@ struct BatchSizes {
 struct BatchLayout {
     size_t row_ptr, col_idx, col_ptr, row_idx, c, wsig, a, x, b, zs, u, v, y_prev, ps_prev;
     size_t link_off, stream_off, lo, hi, ictl, hist, st_seg, st_inst, lt_seg, lt_inst;
-    size_t inst_st, inst_lt, st_part, lt_part, bar, util, sperm, prof, total;
+    size_t inst_st, inst_lt, st_part, lt_part, lt_ck, lt_hsum, lt_hcnt, ifx_shift, ifx_scale;
+    size_t ifx_inv, bar, util, sperm, prof, total;
     long long nst_max, nlt_max;
 };
 
-BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap)
+BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap, int heavy_chunk)
 {
     BatchLayout L{};
     size_t off = 0;
@@ -327,7 +407,9 @@ BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap)
         return o;
     };
     L.nst_max = z.N / kBlock + 2 * z.NNZ / min_cap + 2LL * z.B + 2;
-    L.nlt_max = z.M / kBlock + 2 * z.NNZ / min_cap + 2LL * z.B + 2;
+    // chunk tiles of long rows: at most nnz / heavy_chunk + (long rows) more
+    L.nlt_max = z.M / kBlock + 2 * z.NNZ / min_cap + 2LL * z.B + 2 + z.NNZ / heavy_chunk +
+                z.NNZ / kCap + 1;
     const size_t M = (size_t)z.M, N = (size_t)z.N, E = (size_t)z.NNZ, B = (size_t)z.B;
     L.row_ptr = take((M + 1) * 4);
     L.col_idx = take(E * 4);
@@ -357,6 +439,12 @@ BatchLayout batch_plan(const BatchSizes &z, size_t sz, int min_cap)
     L.inst_lt = take((B + 1) * 4);
     L.st_part = take((size_t)L.nst_max * 8);
     L.lt_part = take((size_t)L.nlt_max * 16);
+    L.lt_ck = take((size_t)L.nlt_max * sizeof(int2));
+    L.lt_hsum = take((size_t)L.nlt_max * 8);
+    L.lt_hcnt = take((size_t)L.nlt_max * 4);
+    L.ifx_shift = take(B * 4);
+    L.ifx_scale = take(B * 8);
+    L.ifx_inv = take(B * 8);
     L.bar = take(16);
     L.util = take(N);
     L.sperm = take(N * 4);
@@ -378,6 +466,8 @@ bool sizes_of(int count, const pmp_problem *pr, BatchSizes &z)
     return z.M < (1LL << 31) && z.N < (1LL << 31) && z.NNZ < (1LL << 31);
 }
 
+int heavy_chunk_of(const pmp_batch_options *o) { return o->heavy_chunk > 0 ? o->heavy_chunk : kLongChunk; }
+
 int class_cap(const pmp_batch_options *o, int m)
 {
     const int c = m < o->class_m[0] ? 0 : (m < o->class_m[1] ? 1 : 2);
@@ -385,12 +475,27 @@ int class_cap(const pmp_batch_options *o, int m)
 }
 
 // Greedy tiles over segments [first, last) of one instance: at most kBlock
-// segments and `cap` nonzeros each (a longer segment alone).
+// segments and `cap` nonzeros each (a longer segment alone).  With `ck`
+// (link rows), a row longer than kCap becomes ceil(len / chunk) chunk tiles
+// that all start at that row.
 void tiles_for(const std::vector<int> &ptr, int first, int last, int cap, int inst,
-               std::vector<int> &seg, std::vector<int> &owner)
+               std::vector<int> &seg, std::vector<int> &owner, int chunk = 0,
+               std::vector<int2> *ck = nullptr)
 {
     int s = first;
     while (s < last) {
+        const long long len = ptr[s + 1] - ptr[s];
+        if (ck && len > kCap) {
+            const int nch = (int)((len + chunk - 1) / chunk);
+            for (int k = 0; k < nch; ++k) {
+                seg.push_back(k + 1 < nch ? s : s + 1);
+                owner.push_back(inst);
+                ck->push_back(make_int2(k, nch));
+            }
+            ++s;
+            continue;
+        }
+        if (ck) ck->push_back(make_int2(0, 0));
         int e = s;
         long long cnt = 0;
         while (e < last && e - s < kBlock && cnt + (ptr[e + 1] - ptr[e]) <= cap) {
@@ -498,7 +603,8 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
                             char *ws, const BatchSizes &z)
 {
     const int min_cap = std::min(opt->tile_cap[0], std::min(opt->tile_cap[1], opt->tile_cap[2]));
-    const BatchLayout L = batch_plan(z, sizeof(T), min_cap);
+    const int chunk = heavy_chunk_of(opt);
+    const BatchLayout L = batch_plan(z, sizeof(T), min_cap, chunk);
     hipStream_t s = b->stream;
     BDev<T> &d = bdev_of<T>(b);
     Dev<T> &g = d.g;
@@ -585,6 +691,13 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     d.inst_lt = (int *)(ws + L.inst_lt);
     d.st_part = (double *)(ws + L.st_part);
     d.lt_part = (double *)(ws + L.lt_part);
+    d.lt_ck = (const int2 *)(ws + L.lt_ck);
+    d.lt_hsum = (long long *)(ws + L.lt_hsum);
+    d.lt_hcnt = (unsigned *)(ws + L.lt_hcnt);
+    d.heavy_chunk = chunk;
+    d.ifx_shift = (const int *)(ws + L.ifx_shift);
+    d.ifx_scale = (const double *)(ws + L.ifx_scale);
+    d.ifx_inv = (const double *)(ws + L.ifx_inv);
     d.bar = (unsigned *)(ws + L.bar);
     d.abort = (int *)(ws + L.bar + 8);
     d.prof = opt->profile ? (unsigned long long *)(ws + L.prof) : nullptr;
@@ -609,14 +722,27 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     std::vector<int> col_ptr((size_t)N + 1);
     BATCH_TRY(hipMemcpyAsync(col_ptr.data(), g.col_ptr, col_ptr.size() * 4, hipMemcpyDeviceToHost, s));
     BATCH_TRY(hipStreamSynchronize(s));
-    // tiles per instance, sized by the instance's class
+    // tiles per instance, sized by the instance's class; long link rows in
+    // chunk tiles, summed in fixed point as in the single-instance layouts
     std::vector<int> st_seg{0}, st_inst, lt_seg{0}, lt_inst, inst_st{0}, inst_lt{0};
+    std::vector<int2> lt_ck;
+    std::vector<int> fx_shift((size_t)B);
+    std::vector<double> fx_scale((size_t)B), fx_inv((size_t)B);
     for (int i = 0; i < B; ++i) {
         const int cap = class_cap(opt, b->m[(size_t)i]);
         tiles_for(col_ptr, b->stream_off[(size_t)i], b->stream_off[(size_t)i + 1], cap, i, st_seg, st_inst);
-        tiles_for(row_ptr, b->link_off[(size_t)i], b->link_off[(size_t)i + 1], cap, i, lt_seg, lt_inst);
+        tiles_for(row_ptr, b->link_off[(size_t)i], b->link_off[(size_t)i + 1], cap, i, lt_seg, lt_inst,
+                  chunk, &lt_ck);
         inst_st.push_back((int)st_inst.size());
         inst_lt.push_back((int)lt_inst.size());
+        long long maxlong = 0;
+        for (int l = b->link_off[(size_t)i]; l < b->link_off[(size_t)i + 1]; ++l) {
+            const long long len = row_ptr[(size_t)l + 1] - row_ptr[(size_t)l];
+            if (len > kCap) maxlong = std::max(maxlong, len);
+        }
+        fx_shift[(size_t)i] = long_row_shift(sizeof(T), maxlong, hi[(size_t)i]);
+        fx_scale[(size_t)i] = std::ldexp(1.0, fx_shift[(size_t)i]);
+        fx_inv[(size_t)i] = std::ldexp(1.0, -fx_shift[(size_t)i]);
     }
     d.nst = (int)st_inst.size();
     d.nlt = (int)lt_inst.size();
@@ -626,6 +752,13 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     if (d.nst) BATCH_TRY(hipMemcpyAsync((void *)d.st_inst, st_inst.data(), st_inst.size() * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.lt_seg, lt_seg.data(), lt_seg.size() * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.lt_inst, lt_inst.data(), lt_inst.size() * 4, hipMemcpyHostToDevice, s));
+    if (d.nlt) {
+        BATCH_TRY(hipMemcpyAsync((void *)d.lt_ck, lt_ck.data(), lt_ck.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        launch_fill_int((int *)d.lt_hcnt, 0, d.nlt, s);
+    }
+    BATCH_TRY(hipMemcpyAsync((void *)d.ifx_shift, fx_shift.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.ifx_scale, fx_scale.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
+    BATCH_TRY(hipMemcpyAsync((void *)d.ifx_inv, fx_inv.data(), (size_t)B * 8, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.inst_st, inst_st.data(), inst_st.size() * 4, hipMemcpyHostToDevice, s));
     BATCH_TRY(hipMemcpyAsync((void *)d.inst_lt, inst_lt.data(), inst_lt.size() * 4, hipMemcpyHostToDevice, s));
 
@@ -721,6 +854,7 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     o->reorder_streams = 1;
     o->wg_per_cu = 2;
     o->profile = 0;
+    o->heavy_chunk = kLongChunk;
     return PMP_OK;
 }
 
@@ -733,6 +867,8 @@ static pmp_status check_batch_args(int32_t count, const pmp_problem *pr, const p
             return set_error(PMP_ERR_INVALID, "tile_cap must be in [64, %d]", kCap);
     if (opt->wg_per_cu < 0 || opt->wg_per_cu > 8)
         return set_error(PMP_ERR_INVALID, "wg_per_cu must be in [0, 8]");
+    if (opt->heavy_chunk != 0 && (opt->heavy_chunk < 1024 || opt->heavy_chunk > (1 << 20)))
+        return set_error(PMP_ERR_INVALID, "heavy_chunk must be 0 or in [1024, 2^20]");
     for (int i = 1; i < count; ++i)
         if (pr[i].dtype != pr[0].dtype) return set_error(PMP_ERR_INVALID, "batch instances must share the dtype");
     if (!sizes_of(count, pr, z)) return set_error(PMP_ERR_SHAPE, "batch sizes out of range (m >= 1; totals < 2^31)");
@@ -755,7 +891,7 @@ pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,
     if (st != PMP_OK) return st;
     if (!bytes) return set_error(PMP_ERR_INVALID, "bytes is NULL");
     const int min_cap = std::min(options->tile_cap[0], std::min(options->tile_cap[1], options->tile_cap[2]));
-    *bytes = batch_plan(z, problems[0].dtype == PMP_F64 ? 8 : 4, min_cap).total;
+    *bytes = batch_plan(z, problems[0].dtype == PMP_F64 ? 8 : 4, min_cap, heavy_chunk_of(options)).total;
     return PMP_OK;
 }
 
@@ -772,7 +908,7 @@ pmp_status pmp_batch_setup(int32_t count, const pmp_problem *problems, const pmp
         if ((st = validate_host(problems[i], i)) != PMP_OK) return st;
     const size_t sz = problems[0].dtype == PMP_F64 ? 8 : 4;
     const int min_cap = std::min(options->tile_cap[0], std::min(options->tile_cap[1], options->tile_cap[2]));
-    const size_t need = batch_plan(z, sz, min_cap).total;
+    const size_t need = batch_plan(z, sz, min_cap, heavy_chunk_of(options)).total;
     if (!workspace || workspace_bytes < need)
         return set_error(PMP_ERR_SHAPE, "batch workspace of %zu bytes needed, %zu given", need, workspace_bytes);
     if ((uintptr_t)workspace % kAlignB) return set_error(PMP_ERR_INVALID, "workspace must be 256-byte aligned");

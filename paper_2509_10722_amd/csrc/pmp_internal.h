@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -20,6 +22,18 @@ constexpr int kCap = 4096;
 // by several workgroups, one per chunk of kLongChunk nonzeros; a second
 // kernel adds the chunk sums in chunk order and runs the link update.
 constexpr int kLongChunk = 8192;
+// Shift F of the fixed-point long-row sums (Dev::fx_shift) of a problem with
+// element size `elem`, longest long row `maxlong` (0 if none) and box upper
+// bound `hi`: the largest F with maxlong x hi x 2^F <= 2^62 (so every term and
+// partial sum fits an int64), at most 126.  0 (plain FP64 sums) for FP64
+// problems, without long rows, with an unbounded box, or where F would fall
+// below 24 (a quantum 2^-F coarser than FP32 rounding).
+inline int long_row_shift(size_t elem, long long maxlong, double hi)
+{
+    if (elem != 4 || maxlong <= 0 || !std::isfinite(hi) || !(hi > 0.0)) return 0;
+    const int F = std::min((int)std::floor(62.0 - std::log2((double)maxlong * hi)), 126);
+    return F >= 24 ? F : 0;
+}
 // Device history ring of (iteration, ||r||, ||s||, rho), one entry per check.
 constexpr int kHist = 4096;
 // Threads of the kernel that reduces the residual partials of a check.
@@ -268,6 +282,20 @@ struct BDev {
     const int *inst_lt;        // [B+1] first link tile of each instance
     double *st_part;           // [nst]
     double *lt_part;           // [2 nlt]
+    // Link rows longer than kCap (congested links) are split into chunk tiles
+    // of heavy_chunk nonzeros: lt_ck[t] = {chunk, chunks of the row} for such
+    // a tile ({0, 0} otherwise), and every chunk tile of a row starts at that
+    // row in lt_seg.  A chunk tile leaves its sum in lt_hsum[t] (FP64 bits,
+    // or int64 in fixed point); the workgroup that counts the row's last
+    // arrival in lt_hcnt[first chunk tile] adds the sums in chunk order and
+    // runs the link update.
+    const int2 *lt_ck;         // [nlt]
+    long long *lt_hsum;        // [nlt]
+    unsigned *lt_hcnt;         // [nlt]
+    int heavy_chunk;
+    const int *ifx_shift;      // [B] fixed-point shift of each instance's long rows
+    const double *ifx_scale;   // [B] 2^shift
+    const double *ifx_inv;     // [B] 2^-shift
     unsigned *bar;             // [2] grid barrier: arrivals, generation
     int *abort;                // set when a barrier wait exceeds its bound
     unsigned long long *prof;  // [grid * kBatchPhases] phase clocks, or NULL

@@ -175,6 +175,37 @@ int main()
             std::vector<int> seg{0}, owner;
             tiles_for(a.row_ptr, 0, a.m, cap, rep, seg, owner);
             REQUIRE(seg.back() == a.m && owner.size() + 1 == seg.size());
+            // link tiles: rows longer than kCap split into chunk tiles that
+            // start at their row and cover it once, within the planned bound
+            for (int chunk : {1024, 3000, 8192}) {
+                std::vector<int> ls{0}, lo;
+                std::vector<int2> ck;
+                tiles_for(a.row_ptr, 0, a.m, cap, rep, ls, lo, chunk, &ck);
+                REQUIRE(ls.back() == a.m && lo.size() + 1 == ls.size() && ck.size() == lo.size());
+                BatchSizes z;
+                z.M = a.m;
+                z.N = a.n;
+                z.NNZ = a.row_ptr[(size_t)a.m];
+                z.B = 1;
+                REQUIRE((long long)lo.size() <= batch_plan(z, 4, cap, chunk).nlt_max);
+                for (size_t t = 0; t < lo.size(); ++t) {
+                    const int l = ls[t], len = a.row_ptr[(size_t)l + 1] - a.row_ptr[(size_t)l];
+                    if (ck[t].y == 0) {
+                        REQUIRE(ls[t + 1] > l);
+                        continue;
+                    }
+                    REQUIRE(len > kCap && ck[t].y == (len + chunk - 1) / chunk);
+                    REQUIRE(ck[t].x == (t > 0 && ck[t - 1].y > 0 && ls[t - 1] == l ? ck[t - 1].x + 1 : 0));
+                    REQUIRE(ls[t + 1] == (ck[t].x + 1 < ck[t].y ? l : l + 1));
+                }
+            }
+        }
+        REQUIRE(long_row_shift(8, 5000, 1.0) == 0 && long_row_shift(4, 0, 1.0) == 0);
+        REQUIRE(long_row_shift(4, 5000, INFINITY) == 0 && long_row_shift(4, 1LL << 30, 1e9) == 0);
+        {
+            const int F = long_row_shift(4, 50013, 1e3);
+            REQUIRE(F >= 24 && std::ldexp(50013.0 * 1e3, F) <= std::ldexp(1.0, 62) &&
+                    std::ldexp(50013.0 * 1e3, F + 1) > std::ldexp(1.0, 62));
         }
         std::vector<double> c, w;
         std::vector<uint8_t> u;

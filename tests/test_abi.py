@@ -133,3 +133,23 @@ def test_null_handles_are_rejected():
                          sizes) == pmp.PMP_ERR_INVALID
     assert lib.pmp_state_size(None, ctypes.byref(b)) == pmp.PMP_ERR_INVALID
     assert lib.pmp_last_error().decode()
+
+
+@pytest.mark.parametrize("chunk,status", [(0, 0), (1024, 0), (8192, 0), (1 << 20, 0),
+                                          (1023, 1), (-5, 1), ((1 << 20) + 1, 1)])
+def test_batch_options_heavy_chunk_range(chunk, status):
+    """pmp_batch_options: defaults, and heavy_chunk accepted as 0 or within
+    [1024, 2^20] by pmp_batch_workspace_size (host-only call)."""
+    from paper_2509_10722_amd import pmp
+    lib = pmp.load_library()
+    o = pmp.batch_options_default()
+    assert (list(o.tile_cap), o.wg_per_cu, o.heavy_chunk) == ([4096] * 3, 2, 8192)
+    o.heavy_chunk = chunk
+    prob = pmp.pmp_problem(m=10, n=20, nnz=50, dtype=pmp.PMP_F32)
+    prm = pmp.params_default()
+    b = ctypes.c_size_t()
+    st = lib.pmp_batch_workspace_size(1, ctypes.byref(prob), ctypes.byref(prm), ctypes.byref(o),
+                                      ctypes.byref(b))
+    assert st == (pmp.PMP_ERR_INVALID if status else 0)
+    if not status:
+        assert b.value > 0 and b.value % 256 == 0

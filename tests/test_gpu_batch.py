@@ -172,3 +172,83 @@ def test_batch_results_independent_of_instance_order():
     for k in range(len(insts)):
         a, c = runs[0][k], runs[1][k]
         assert a[0] == c[0] and np.array_equal(a[1], c[1]) and np.array_equal(a[2], c[2])
+
+
+def _congested_batch(dtype_name):
+    """Two congested instances (Section V-C: 0.1% of the links on 10% of the
+    streams; rows of 5,000 and 10,000 nonzeros) beside a transit instance."""
+    insts = [I.congested(I.medium(scale=0.1), seed=6),
+             I.batched(count=1, scale=0.01)[0],
+             I.congested(I.medium(seed=7, scale=0.2), seed=9)]
+    return [i.rounded(np.float32) for i in insts] if dtype_name == "float32" else insts
+
+
+@pytest.mark.parametrize("dtype_name,chunk", [("float32", 1024), ("float32", 8192),
+                                              ("float32", 1 << 20), ("float64", 8192)])
+def test_congested_batch_matches_plain_gather_solves(dtype_name, chunk):
+    """Long link rows in chunk tiles (heavy_chunk) finished by the last
+    arriving workgroup: the iterates equal those of one-at-a-time solves in
+    the gather layout bit for bit.  In FP32 (finite box) the long rows are
+    exact fixed-point sums, so any chunk size gives them; in FP64 the 8192
+    chunks are the gather layout's own."""
+    dtype = getattr(torch, dtype_name)
+    insts = _congested_batch(dtype_name)
+    K = 300
+    print(f"congested batch {dtype_name}, heavy_chunk {chunk}, {K} iterations", flush=True)
+    b = BatchSolver(insts, dtype=dtype, eps_abs=0.0,
+                    options=batch_options_default(heavy_chunk=chunk))
+    res = b.solve(K)
+    for k, inst in enumerate(insts):
+        s = Solver(inst, dtype=dtype, layout=1, eps_abs=0.0, max_iter=K)
+        r = s.solve()
+        x, lam, _ = s.solution()
+        xb, lb, _ = b.solution(k)
+        deg = int(np.diff(inst.row_ptr).max())
+        print(f"  instance {k} (m={inst.m}, longest row {deg}): batch rho {res[k]['rho']}, "
+              f"plain rho {r['rho']}", flush=True)
+        assert res[k]["iterations"] == r["iterations"] == K
+        assert res[k]["rho"] == r["rho"]
+        assert torch.equal(x, xb) and torch.equal(lam, lb)
+        s.close()
+    b.close()
+
+
+def test_congested_batch_fp64_small_chunks_repeat():
+    """FP64 long rows in chunks of 1024 (other chunk sums than the gather
+    layout's): two solves from the same start agree bit for bit whatever
+    workgroup arrives last, and stay within rounding of the plain solve."""
+    insts = _congested_batch("float64")
+    K = 200
+    b = BatchSolver(insts, dtype=torch.float64, eps_abs=0.0,
+                    options=batch_options_default(heavy_chunk=1024))
+    runs = []
+    for _ in range(2):
+        b.reset()
+        b.solve(K)
+        runs.append([host(b.solution(k)[0]) for k in range(len(insts))])
+    for a, c in zip(*runs):
+        assert np.array_equal(a, c)
+    for k, inst in enumerate(insts):
+        s = Solver(inst, dtype=torch.float64, layout=1, eps_abs=0.0, max_iter=K)
+        s.solve()
+        x = host(s.solution()[0])
+        s.close()
+        assert np.max(np.abs(runs[0][k] - x)) <= 1e-9 * max(1.0, np.max(np.abs(x)))
+    b.close()
+
+
+def test_autotuner_heavy_row_class(tmp_path):
+    """With congested instances present the tuner times the long-row chunk
+    candidates and caches the choice (per architecture) next to the tile caps."""
+    from paper_2509_10722_amd import autotune
+    insts = _congested_batch("float32")
+    path = str(tmp_path / "tiles.json")
+    opts, timings = autotune.tune_batch(insts, dtype=torch.float32, iters=20, reps=1,
+                                        candidates=(1024, 4096), heavy_candidates=(1024, 8192),
+                                        path=path)
+    print({k: round(v * 1e3, 3) for k, v in timings.items()}, flush=True)
+    assert {"heavy:1024", "heavy:8192"} <= set(timings)
+    assert autotune.cached_options(torch, path).heavy_chunk == opts.heavy_chunk in (1024, 8192)
+    plain = autotune.tune_batch([I.batched(count=1, scale=0.01)[0]], dtype=torch.float32,
+                                iters=10, reps=1, candidates=(4096,), path=path)[1]
+    assert not any(k.startswith("heavy:") for k in plain)

@@ -108,3 +108,13 @@ def test_transit_case_study_small():
     inst, meta = I.transit_case_study(stations=12, T=16, edges=30, od_pairs=6, departures=4)
     _check_pattern(inst)
     assert inst.m == 30 * 16 and inst.n == 6 * 2 * 4
+
+
+def test_heavy_row_class_detection():
+    """The autotuner's heavy-row class: instances with a link row longer than
+    4096 nonzeros (congested links at 10% of 5e4 streams), not plain ones."""
+    from paper_2509_10722_amd import autotune
+    base = I.medium(scale=0.1)
+    assert not autotune.has_heavy_rows(base)
+    assert autotune.has_heavy_rows(I.congested(base))
+    assert not autotune.has_heavy_rows(I.congested(I.medium(scale=0.05)))   # rows of 2,500
