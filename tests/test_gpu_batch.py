@@ -252,3 +252,27 @@ def test_autotuner_heavy_row_class(tmp_path):
     plain = autotune.tune_batch([I.batched(count=1, scale=0.01)[0]], dtype=torch.float32,
                                 iters=10, reps=1, candidates=(4096,), path=path)[1]
     assert not any(k.startswith("heavy:") for k in plain)
+
+
+def test_congested_batch_to_tolerance_matches_plain():
+    """Solved to the 1e-4 rule, the instances stop at different checks (a
+    stopped instance's chunk tiles are skipped while the others run on); every
+    instance stops at the plain gather solve's iteration with its iterate bit
+    for bit (FP32, fixed-point long rows, chunks of 1024)."""
+    insts = _congested_batch("float32")
+    b = BatchSolver(insts, dtype=torch.float32, options=batch_options_default(heavy_chunk=1024))
+    res = b.solve(30000)
+    its = []
+    for k, inst in enumerate(insts):
+        s = Solver(inst, dtype=torch.float32, layout=1, max_iter=30000)
+        r = s.solve()
+        x, lam, _ = s.solution()
+        xb, lb, _ = b.solution(k)
+        print(f"  instance {k}: batch {res[k]['iterations']} it, plain {r['iterations']} it", flush=True)
+        assert res[k]["converged"] and r["converged"]
+        assert res[k]["iterations"] == r["iterations"]
+        assert torch.equal(x, xb) and torch.equal(lam, lb)
+        its.append(r["iterations"])
+        s.close()
+    b.close()
+    assert len(set(its)) > 1
