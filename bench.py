@@ -168,7 +168,8 @@ def bench_batched_congested(args, log):
     from paper_2509_10722_amd.pmp import BatchSolver, Solver
 
     base = instances.batched(scale=args.scale)
-    insts = [instances.congested(i, seed=100 + k).rounded(np.float32) for k, i in enumerate(base)]
+    insts = [instances.congested(i, link_frac=args.link_frac, stream_frac=args.stream_frac,
+                                 seed=100 + k).rounded(np.float32) for k, i in enumerate(base)]
     del base
     tot = {"m": sum(i.m for i in insts), "n": sum(i.n for i in insts),
            "nnz": sum(i.nnz for i in insts),
@@ -184,6 +185,7 @@ def bench_batched_congested(args, log):
         opts.heavy_chunk = args.heavy_chunk
 
     def batched(chunk):
+        """Time K iterations with long rows in chunks of `chunk` nonzeros."""
         opts.heavy_chunk = chunk
         b = BatchSolver(insts, dtype=torch.float32, options=opts, eps_abs=0.0)
         b.solve(20)
@@ -200,6 +202,10 @@ def bench_batched_congested(args, log):
     chunk = int(opts.heavy_chunk)
     tb, xb = batched(chunk)
     log(f"[bench] heavy_chunk {chunk}: {K} iterations in {tb:.3f} s")
+    others = {}
+    for c in args.chunk_sweep:
+        others[c] = batched(c)[0]
+        log(f"[bench] heavy_chunk {c}: {K} iterations in {others[c]:.3f} s")
     t1, x1 = batched(1 << 20)
     log(f"[bench] one workgroup per long row: {K} iterations in {t1:.3f} s")
     same = all(torch.equal(a, c) for a, c in zip(xb, x1))
@@ -220,10 +226,12 @@ def bench_batched_congested(args, log):
         "value": round(len(insts) * K / tb, 1), "unit": "instance-iter/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"congested batched transit x{len(insts)}", **tot, "K": K,
-                   "heavy_chunk": chunk},
+                   "heavy_chunk": chunk, "link_frac": args.link_frac,
+                   "stream_frac": args.stream_frac},
         "time_s": round(tb, 4), "row_per_workgroup_time_s": round(t1, 4),
         "chunking_speedup": round(t1 / tb, 3), "plain_time_s": round(tp, 4),
         "speedup_vs_plain": round(tp / tb, 3), "iterates_equal_across_chunks": bool(same),
+        "chunk_sweep_s": {str(c): round(t, 4) for c, t in others.items()},
     }
     print(json.dumps(line), flush=True)
 
@@ -511,6 +519,12 @@ def main():
                          "eps_rel = 1e-4)")
     ap.add_argument("--congested", action="store_true",
                     help="batched: congested transit instances (Section V-C), fixed iterations")
+    ap.add_argument("--link-frac", type=float, default=0.001,
+                    help="batched --congested: fraction of each instance's links made hot")
+    ap.add_argument("--stream-frac", type=float, default=0.1,
+                    help="batched --congested: fraction of the streams each hot link carries")
+    ap.add_argument("--chunk-sweep", type=int, nargs="*", default=[],
+                    help="batched --congested: also time these heavy_chunk values")
     ap.add_argument("--heavy-chunk", type=int, default=0,
                     help="batched: nonzeros per chunk of a long link row (0: cached or default)")
     ap.add_argument("--batch-only", action="store_true",

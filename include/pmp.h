@@ -311,7 +311,7 @@ typedef struct {
     int32_t tile_cap[3];
     int32_t reorder_streams;
     int32_t wg_per_cu;      /* resident workgroups per CU in the persistent grid
-                               (1..8, capped by occupancy; 0 = 2) */
+                               (1..8, capped by occupancy; 0 = 4) */
     int32_t profile;        /* 1: time the kernel's phases (pmp_batch_profile) */
     int32_t heavy_chunk;    /* link rows of more than 4096 nonzeros (congested
                                links, Section V-C) are split into chunks of this
@@ -324,7 +324,7 @@ typedef struct {
 } pmp_batch_options;
 
 /* Defaults (tuned on MI355X for transit batches): classes at m = 1e4 and
- * 5e4, tile caps 4096 for every class, reorder_streams 1, wg_per_cu 2,
+ * 5e4, tile caps 4096 for every class, reorder_streams 1, wg_per_cu 4,
  * heavy_chunk 8192. */
 pmp_status pmp_batch_options_default(pmp_batch_options *options);
 pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,

@@ -296,7 +296,7 @@ struct BDev {
     const int *ifx_shift;      // [B] fixed-point shift of each instance's long rows
     const double *ifx_scale;   // [B] 2^shift
     const double *ifx_inv;     // [B] 2^-shift
-    unsigned *bar;             // [2] grid barrier: arrivals, generation
+    unsigned *bar;             // grid barrier: counters, generation (pmp_batch.hip)
     int *abort;                // set when a barrier wait exceeds its bound
     unsigned long long *prof;  // [grid * kBatchPhases] phase clocks, or NULL
 };
