@@ -537,7 +537,7 @@ def main():
               "for hours on the larger ones)", file=sys.stderr)
         sys.exit(2)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
