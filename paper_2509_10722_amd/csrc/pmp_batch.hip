@@ -168,10 +168,12 @@ __device__ bool link_chunk(const BDev<T> &d, const Dev<T> &di, int inst, int til
         const int t0 = tile - k;
         last = true;
         if (nch > 1) {
+            // release before the arrival, acquire only in the last arrival
+            // (each an L2 writeback or invalidate on this GPU)
             __hip_atomic_store(&d.lt_hsum[tile], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             last = atomicAdd(&d.lt_hcnt[t0], 1u) == (unsigned)(nch - 1);
-            if (last) __threadfence();
+            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (last) {
             double y = 0.0;
