@@ -321,11 +321,14 @@ typedef struct {
                                in fixed point, so there the results do not depend
                                on it; otherwise 8192 gives the sums of pmp_solve's
                                gather layout */
+    int32_t wait_log2;      /* a grid barrier wait gives up after 2^wait_log2
+                               polls (0 or [1, 30]; 0 = 24);
+                               pmp_batch_solve then returns PMP_ERR_HIP */
 } pmp_batch_options;
 
 /* Defaults (tuned on MI355X for transit batches): classes at m = 1e4 and
  * 5e4, tile caps 4096 for every class, reorder_streams 1, wg_per_cu 4,
- * heavy_chunk 8192. */
+ * heavy_chunk 8192, wait_log2 24. */
 pmp_status pmp_batch_options_default(pmp_batch_options *options);
 pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,
                                     const pmp_params *params, const pmp_batch_options *options,

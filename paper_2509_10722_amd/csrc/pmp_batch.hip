@@ -28,7 +28,9 @@ namespace pmp {
 
 namespace {
 
-constexpr unsigned long long kSpinLimit = 1ull << 24;
+// A barrier wait polls at most 2^wait_log2 times (2^24 by default), then
+// sets the abort flag.
+constexpr int kWaitLog2Default = 24;
 
 // Grid barrier in two levels.  Blocks are dealt to the 8 XCDs in turn, so
 // the blocks with one value of blockIdx.x mod 8 (one XCD) first meet on their
@@ -46,7 +48,7 @@ constexpr unsigned long long kSpinLimit = 1ull << 24;
 constexpr int kBarTop = 0, kBarGen = 64, kBarAbort = 128, kBarGroup = 192;
 constexpr int kBarWords = kBarGroup + 64 * 8;   // unsigned words of BDev::bar
 
-__device__ bool grid_sync(unsigned *bar, int *abort, unsigned nblocks)
+__device__ bool grid_sync(unsigned *bar, int *abort, unsigned nblocks, unsigned long long spin_limit)
 {
     __shared__ int s_ok;
     __syncthreads();
@@ -74,7 +76,7 @@ __device__ bool grid_sync(unsigned *bar, int *abort, unsigned nblocks)
             unsigned long long spins = 0;
             while (__hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit ||
+                if (++spins > spin_limit ||
                     __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     atomicExch(abort, 1);
                     ok = 0;
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
         d.ictl[i].done = 0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.nlt; t += G * blockDim.x)
         d.lt_hcnt[t] = 0;
-    if (!grid_sync(d.bar, d.abort, G)) return;
+    if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
     long long last_check = 0;
     for (int it = 1; it <= max_iter; ++it) {
         const bool check = it % ce == 0 || it == max_iter;
@@ -293,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
             else stream_tile<T, false>(d, t, sv, sred);
         }
         lap(0);
-        if (!grid_sync(d.bar, d.abort, G)) return;
+        if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
         lap(1);
         for (int t = blockIdx.x; t < d.nlt; t += G) {
             if (check) link_tile<T, kCheck>(d, t, sv, sred);
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
             else link_tile<T, kPlain>(d, t, sv, sred);
         }
         lap(2);
-        if (!grid_sync(d.bar, d.abort, G)) return;
+        if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
         lap(3);
         if (!check) continue;
         // finalize: one workgroup per instance, partials in tile order
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
             if (threadIdx.x == 0) finalize<T>(instance_view(d, i), delta, 1, sr, ss + sl);
             __syncthreads();
         }
-        if (!grid_sync(d.bar, d.abort, G)) return;
+        if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
         lap(4);
         int active = 0;
         bool rescale = false;
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
                     d.g.v[l] = (T)((double)d.g.b[l] - (double)ut);
                 }
             }
-            if (!grid_sync(d.bar, d.abort, G)) return;
+            if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
         }
     }
     lap(5);
@@ -724,6 +726,7 @@ pmp_status batch_setup_impl(pmp_batch *b, const pmp_problem *pr, const pmp_batch
     d.lt_hsum = (long long *)(ws + L.lt_hsum);
     d.lt_hcnt = (unsigned *)(ws + L.lt_hcnt);
     d.heavy_chunk = chunk;
+    d.spin_limit = 1ull << (opt->wait_log2 > 0 ? opt->wait_log2 : kWaitLog2Default);
     d.ifx_shift = (const int *)(ws + L.ifx_shift);
     d.ifx_scale = (const double *)(ws + L.ifx_scale);
     d.ifx_inv = (const double *)(ws + L.ifx_inv);
@@ -884,6 +887,7 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     o->wg_per_cu = 4;
     o->profile = 0;
     o->heavy_chunk = kLongChunk;
+    o->wait_log2 = kWaitLog2Default;
     return PMP_OK;
 }
 
@@ -898,6 +902,8 @@ static pmp_status check_batch_args(int32_t count, const pmp_problem *pr, const p
         return set_error(PMP_ERR_INVALID, "wg_per_cu must be in [0, 8]");
     if (opt->heavy_chunk != 0 && (opt->heavy_chunk < 1024 || opt->heavy_chunk > (1 << 20)))
         return set_error(PMP_ERR_INVALID, "heavy_chunk must be 0 or in [1024, 2^20]");
+    if (opt->wait_log2 < 0 || opt->wait_log2 > 30)
+        return set_error(PMP_ERR_INVALID, "wait_log2 must be in [0, 30]");
     for (int i = 1; i < count; ++i)
         if (pr[i].dtype != pr[0].dtype) return set_error(PMP_ERR_INVALID, "batch instances must share the dtype");
     if (!sizes_of(count, pr, z)) return set_error(PMP_ERR_SHAPE, "batch sizes out of range (m >= 1; totals < 2^31)");

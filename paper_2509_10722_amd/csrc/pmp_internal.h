@@ -293,6 +293,7 @@ struct BDev {
     long long *lt_hsum;        // [nlt]
     unsigned *lt_hcnt;         // [nlt]
     int heavy_chunk;
+    unsigned long long spin_limit;   // polls of a barrier wait before it gives up
     const int *ifx_shift;      // [B] fixed-point shift of each instance's long rows
     const double *ifx_scale;   // [B] 2^shift
     const double *ifx_inv;     // [B] 2^-shift

@@ -425,7 +425,8 @@ def pmp_objective(c, w, solver, K, s=25):
 class pmp_batch_options(ctypes.Structure):
     _fields_ = [("class_m", ctypes.c_int32 * 2), ("tile_cap", ctypes.c_int32 * 3),
                 ("reorder_streams", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
+                ("wait_log2", ctypes.c_int32)]
 
 
 _BATCH_SIGNATURES = {
@@ -456,7 +457,7 @@ def batch_options_default(**caps) -> pmp_batch_options:
             o.class_m[i] = int(v)
     if "reorder_streams" in caps:
         o.reorder_streams = int(caps["reorder_streams"])
-    for key in ("wg_per_cu", "profile", "heavy_chunk"):
+    for key in ("wg_per_cu", "profile", "heavy_chunk", "wait_log2"):
         if key in caps:
             setattr(o, key, int(caps[key]))
     return o

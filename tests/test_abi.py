@@ -153,3 +153,21 @@ def test_batch_options_heavy_chunk_range(chunk, status):
     assert st == (pmp.PMP_ERR_INVALID if status else 0)
     if not status:
         assert b.value > 0 and b.value % 256 == 0
+
+
+@pytest.mark.parametrize("k,ok", [(0, True), (1, True), (24, True), (30, True), (-1, False),
+                                  (31, False)])
+def test_batch_options_wait_bound_range(k, ok):
+    """pmp_batch_options.wait_log2 (the bound of a grid barrier wait, 2^k
+    polls): default 24, accepted in [0, 30]."""
+    from paper_2509_10722_amd import pmp
+    lib = pmp.load_library()
+    o = pmp.batch_options_default()
+    assert o.wait_log2 == 24
+    o.wait_log2 = k
+    prob = pmp.pmp_problem(m=10, n=20, nnz=50, dtype=pmp.PMP_F32)
+    prm = pmp.params_default()
+    b = ctypes.c_size_t()
+    st = lib.pmp_batch_workspace_size(1, ctypes.byref(prob), ctypes.byref(prm), ctypes.byref(o),
+                                      ctypes.byref(b))
+    assert st == (0 if ok else pmp.PMP_ERR_INVALID)

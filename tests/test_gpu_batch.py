@@ -276,3 +276,26 @@ def test_congested_batch_to_tolerance_matches_plain():
         s.close()
     b.close()
     assert len(set(its)) > 1
+
+
+def test_barrier_wait_bound_reports_error_and_gpu_recovers():
+    """A grid barrier wait bounded at 2 polls (wait_log2 = 1) expires at once:
+    every workgroup leaves the kernel, pmp_batch_solve returns PMP_ERR_HIP, and
+    a batch set up afterwards with the default bound solves as usual."""
+    from paper_2509_10722_amd.pmp import PMP_ERR_HIP, PMPError
+    insts = [i.rounded(np.float32) for i in _small_batch(count=3)]
+    print("batch with wait_log2 = 1 (forced barrier expiry)", flush=True)
+    b = BatchSolver(insts, dtype=torch.float32, options=batch_options_default(wait_log2=1))
+    with pytest.raises(PMPError) as e:
+        b.solve(50)
+    assert e.value.status == PMP_ERR_HIP
+    b.close()
+    print("batch with the default bound", flush=True)
+    good = BatchSolver(insts, dtype=torch.float32)
+    res = good.solve(20000)
+    good.close()
+    ref = BatchSolver(insts, dtype=torch.float32)
+    res2 = ref.solve(20000)
+    ref.close()
+    assert all(r["converged"] for r in res)
+    assert [r["iterations"] for r in res] == [r["iterations"] for r in res2]
