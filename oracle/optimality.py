@@ -102,8 +102,11 @@ def kkt_report(inst, x, lam):
         & (x < inst.hi * (1 - 1e-9))
     interior = (log | a2) & inner
     if np.any(interior):
-        # marginal utility U'(x): w / x (log), w / x^2 (alpha = 2)
-        marg = np.where(log, inst.w / np.maximum(x, 1e-300), inst.w / np.maximum(x, 1e-300) ** 2)
+        # marginal utility U'(x): w / x (log), w / x^2 (alpha = 2); only the
+        # interior entries are used, so an infinite value at x = 0 is harmless
+        with np.errstate(divide="ignore", over="ignore"):
+            marg = np.where(log, inst.w / np.maximum(x, 1e-300),
+                            inst.w / np.maximum(x, 1e-300) ** 2)
         rep["stationarity_log"] = float(np.max(np.abs(marg[interior] - pi[interior]) /
                                                np.maximum(marg[interior], 1e-300)))
     else:
