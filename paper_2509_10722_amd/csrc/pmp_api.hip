@@ -416,6 +416,13 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         d.Q = bp.Q;
         d.LB = bp.LB;
         d.SB = bp.SB;
+        // the binned passes keep two workgroups per CU resident
+        {
+            int dev = 0, cus = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            d.SR = std::max(8, 2 * cus);
+        }
         d.lbs = (const int *)(ws + L.lbs);
         d.sbs = (const int *)(ws + L.sbs);
         // one byte per route length / link degree instead of two pointer
