@@ -66,15 +66,16 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks)
 }
 
 // Stream blocks in descending rounds: dispatch round r (blocks [R r, R r + R),
-// R = Dev::SR, the workgroups the GPU holds at once) takes the r-th range of
-// R stream blocks from the top, and inside a round every XCD takes a run of
+// R = Dev::SR, one per CU) takes the r-th range of R stream blocks from the
+// top, and inside a round every XCD takes a run of
 // consecutive blocks (so the tiles that neighbouring workgroups write are
 // neighbours, as with xcd_block).  The link pass writes the v-message tiles in
 // ascending stream-block order, so the first stream blocks read the tiles
 // written last, which the 256 MB memory-side cache may still hold; likewise
 // the last stream blocks write the x-message tiles that every link block
 // reads first.  Measured on the large workload: stream pass 0.385 -> 0.368 ms,
-// link pass 0.352 -> 0.336 ms, against xcd_block numbering.
+// link pass 0.352 -> 0.336 ms, against xcd_block numbering (rounds of two
+// blocks per CU; one per CU gains another 1%).
 __device__ __forceinline__ int stream_block(int b, int nblocks, int R)
 {
     constexpr int X = 8;
@@ -89,7 +90,8 @@ __device__ __forceinline__ int stream_block(int b, int nblocks, int R)
 // Add messages msg[e0..e1) into acc[idx[e]] (FP64 LDS atomics).  FP32
 // messages are read four at a time (16-byte message and 8-byte index loads,
 // aligned; the arrays carry 4 entries of padding), entries outside
-// [e0, e1) being masked.
+// [e0, e1) being masked.  Messages are loaded non-temporally; indices too,
+// unless TIDX.
 //
 // RUNS (link side): inside a tile the x messages are grouped by link, so a
 // link with many streams in the tile (a congested link) makes a long run of one
@@ -105,7 +107,7 @@ __device__ __forceinline__ int stream_block(int b, int nblocks, int R)
 // entry adds fx_term(x, fxs) with an integer atomic, and merged runs of such
 // a row add the integer sum of their terms, so the row's total does not
 // depend on the order of the adds.
-template <typename T, bool RUNS, bool FX = false>
+template <typename T, bool RUNS, bool FX = false, bool TIDX = false>
 __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
                                            const uint16_t *__restrict__ idx, int e0, int e1,
                                            acc_t *acc, double fxs = 0.0)
@@ -139,7 +141,8 @@ __device__ __forceinline__ void accumulate(const T *__restrict__ msg,
             u4 k = {0, 0, 0, 0};
             if (in) {
                 v = __builtin_nontemporal_load(m4 + b);
-                k = __builtin_nontemporal_load(i4 + b);
+                if (TIDX) k = i4[b];
+                else k = __builtin_nontemporal_load(i4 + b);
             }
             const int e = b << 2;
             if constexpr (RUNS) {
@@ -286,7 +289,11 @@ PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
     const int ns = d.sbs[q + 1] - j0;
     for (int i = threadIdx.x; i < ns; i += kBinThreads) S[i] = 0.0;
     __syncthreads();
-    accumulate<T, false>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
+    // the local stream indices are loaded as ordinary (temporal) data: the
+    // emission below reads them again, and on the large workload that read
+    // then hits more often (stream pass 0.367 -> 0.359 ms; on the link side
+    // the same hint slows the link pass, so there they stay non-temporal)
+    accumulate<T, false, false, true>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
     __syncthreads();
     const double rho = d.ctl->rho;
     double part = 0.0;

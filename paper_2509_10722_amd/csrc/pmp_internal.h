@@ -125,7 +125,7 @@ struct Dev {
     // links and Q stream blocks of at most SB streams tile R into P x Q tiles.
     int binned;                     // 1: iterations use the binned kernels
     int P, Q, LB, SB;
-    int SR;                         // stream blocks per dispatch round (resident workgroups)
+    int SR;                         // stream blocks per dispatch round of the stream pass
     const int *lbs, *sbs;           // [P+1], [Q+1] first link / stream of each block
     const uint8_t *rlen;            // [n] route lengths when all are below 256, else NULL
     const uint8_t *dlen;            // [m] link degrees when all are below 256, else NULL
