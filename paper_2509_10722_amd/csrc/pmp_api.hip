@@ -416,14 +416,17 @@ pmp_status setup_impl(pmp_handle *h, const pmp_problem *p, char *ws)
         d.Q = bp.Q;
         d.LB = bp.LB;
         d.SB = bp.SB;
-        // stream blocks per dispatch round: one per CU (rounds of 1/4 to 4
-        // blocks per CU measured within 2% of each other on the large
-        // workload, one per CU the fastest)
+        // stream blocks per dispatch round: one per CU when the stream blocks
+        // outnumber the two per CU that are resident at once (rounds of 1/4
+        // to 4 blocks per CU measured within 2% of each other on the large
+        // workload, one per CU the fastest); otherwise all of them in one
+        // round, so each XCD keeps a single run of consecutive blocks (split
+        // rounds cost the paper-shape stream pass 6%)
         {
             int dev = 0, cus = 0;
             HIP_TRY(hipGetDevice(&dev));
             HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            d.SR = std::max(8, cus);
+            d.SR = d.Q <= 2 * cus ? std::max(1, d.Q) : std::max(8, cus);
         }
         d.lbs = (const int *)(ws + L.lbs);
         d.sbs = (const int *)(ws + L.sbs);

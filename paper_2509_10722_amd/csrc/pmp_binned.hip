@@ -278,7 +278,7 @@ __device__ __forceinline__ void emit_tiles(const int *__restrict__ src_off,
 #define PMP_BIN_KERNEL __global__ __launch_bounds__(kBinThreads)
 #endif
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool TIDX>
 PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
 {
     if (d.ctl->done) return;
@@ -289,11 +289,14 @@ PMP_BIN_KERNEL void k_bin_stream(Dev<T> d)
     const int ns = d.sbs[q + 1] - j0;
     for (int i = threadIdx.x; i < ns; i += kBinThreads) S[i] = 0.0;
     __syncthreads();
-    // the local stream indices are loaded as ordinary (temporal) data: the
-    // emission below reads them again, and on the large workload that read
-    // then hits more often (stream pass 0.367 -> 0.359 ms; on the link side
-    // the same hint slows the link pass, so there they stay non-temporal)
-    accumulate<T, false, false, true>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
+    // TIDX (chosen at launch when the stream blocks take several dispatch
+    // rounds): the local stream indices are loaded as ordinary (temporal)
+    // data, since the emission below reads them again; on the large workload
+    // that read then hits more often (stream pass 0.367 -> 0.359 ms).  With
+    // every stream block resident at once (the paper shape) the same hint
+    // costs 6%, and on the link side it slows the link pass: there the
+    // indices stay non-temporal.
+    accumulate<T, false, false, TIDX>(d.mv, d.six, d.ov[(long long)q * d.P], d.ov[(long long)(q + 1) * d.P], S);
     __syncthreads();
     const double rho = d.ctl->rho;
     double part = 0.0;
@@ -507,12 +510,18 @@ void binned_configure()
 {
     const int bytes = kBinMaxBlock * (int)sizeof(acc_t);
 #define PMP_BIN_ATTR(K) (void)hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, bytes)
-    PMP_BIN_ATTR((k_bin_stream<float, kPlain>));
-    PMP_BIN_ATTR((k_bin_stream<float, kSave>));
-    PMP_BIN_ATTR((k_bin_stream<float, kCheck>));
-    PMP_BIN_ATTR((k_bin_stream<double, kPlain>));
-    PMP_BIN_ATTR((k_bin_stream<double, kSave>));
-    PMP_BIN_ATTR((k_bin_stream<double, kCheck>));
+    PMP_BIN_ATTR((k_bin_stream<float, kPlain, false>));
+    PMP_BIN_ATTR((k_bin_stream<float, kSave, false>));
+    PMP_BIN_ATTR((k_bin_stream<float, kCheck, false>));
+    PMP_BIN_ATTR((k_bin_stream<double, kPlain, false>));
+    PMP_BIN_ATTR((k_bin_stream<double, kSave, false>));
+    PMP_BIN_ATTR((k_bin_stream<double, kCheck, false>));
+    PMP_BIN_ATTR((k_bin_stream<float, kPlain, true>));
+    PMP_BIN_ATTR((k_bin_stream<float, kSave, true>));
+    PMP_BIN_ATTR((k_bin_stream<float, kCheck, true>));
+    PMP_BIN_ATTR((k_bin_stream<double, kPlain, true>));
+    PMP_BIN_ATTR((k_bin_stream<double, kSave, true>));
+    PMP_BIN_ATTR((k_bin_stream<double, kCheck, true>));
     PMP_BIN_ATTR((k_bin_link<float, kPlain>));
     PMP_BIN_ATTR((k_bin_link<float, kSave>));
     PMP_BIN_ATTR((k_bin_link<float, kCheck>));
@@ -534,15 +543,19 @@ template <typename T>
 void launch_bin_stream(const Dev<T> &d, int mode, hipStream_t s)
 {
     const size_t lds = (size_t)d.SB * sizeof(acc_t);
+    const bool rounds = d.SR < d.Q;   // several dispatch rounds: temporal index loads
     switch (mode) {
     case kPlain:
-        hipLaunchKernelGGL((k_bin_stream<T, kPlain>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        if (rounds) hipLaunchKernelGGL((k_bin_stream<T, kPlain, true>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        else hipLaunchKernelGGL((k_bin_stream<T, kPlain, false>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
         break;
     case kSave:
-        hipLaunchKernelGGL((k_bin_stream<T, kSave>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        if (rounds) hipLaunchKernelGGL((k_bin_stream<T, kSave, true>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        else hipLaunchKernelGGL((k_bin_stream<T, kSave, false>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
         break;
     default:
-        hipLaunchKernelGGL((k_bin_stream<T, kCheck>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        if (rounds) hipLaunchKernelGGL((k_bin_stream<T, kCheck, true>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
+        else hipLaunchKernelGGL((k_bin_stream<T, kCheck, false>), dim3(d.Q), dim3(kBinThreads), lds, s, d);
         break;
     }
 }
