@@ -33,10 +33,12 @@ def _run(inst, K, dtype, layout, **kw):
     return out
 
 
-# large at 0.15: 3e6 streams, a few hundred stream blocks, so the stream pass
-# runs more than one dispatch round of one block per CU and a ragged last one
+# large at 0.15: 3e6 streams, a few hundred stream blocks, all resident at
+# once (one dispatch round); at 0.3: 6e6 streams and more stream blocks than
+# the GPU holds at once, so the stream pass runs in several descending rounds
+# with temporal index loads
 @pytest.mark.parametrize("name,scale", [("medium", 0.2), ("large", 0.01), ("tiny", 1.0),
-                                        ("large", 0.15)])
+                                        ("large", 0.15), ("large", 0.3)])
 def test_binned_equals_gather_fp32(name, scale):
     inst = I.make(name, scale=scale).rounded(np.float32)
     K = 120
