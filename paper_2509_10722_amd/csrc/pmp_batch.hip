@@ -4,9 +4,9 @@
 // instance kept together, indices global), so the stream and link passes of
 // all instances are the same segmented gather-sums as for one instance.  A
 // persistent kernel (grid sized to what the GPU holds at once) walks the
-// iterations: in each phase every workgroup takes every G-th tile of the
-// phase's tile list, skipping tiles of instances that have stopped, and a
-// grid barrier separates the phases.  Check iterations add a finalize phase
+// iterations: in each phase the workgroups of one XCD share a contiguous
+// eighth of the phase's tile list (xcd_tiles), skipping tiles of instances
+// that have stopped, and a grid barrier separates the phases.  Check iterations add a finalize phase
 // (workgroup i reduces instance i's tile partials in a fixed order and takes
 // its stop and rho decisions, Section III-F/G) and, at balancing iterations,
 // a rescale phase.  Tiles never straddle two instances; their size limit is
@@ -260,6 +260,25 @@ __device__ __forceinline__ int find_instance(const int *off, int B, int idx)
     return lo;
 }
 
+// The tiles of a phase [0, count) dealt to the grid: the blocks with one
+// value of blockIdx.x mod X (X = min(G, 8); one XCD, as the hardware deals
+// blocks to XCDs in turn) take one contiguous eighth of the tile list, in
+// turn.  Neighbouring tiles (mostly of one instance) then share an L2:
+// 1.39 s against 1.41 s for the 64-instance transit solve with the tiles dealt
+// to all blocks in turn.
+struct TileRange {
+    int t, end, step;
+};
+__device__ __forceinline__ TileRange xcd_tiles(int count, unsigned G)
+{
+    const int X = (int)min(G, 8u);
+    const int x = (int)blockIdx.x % X, i = (int)blockIdx.x / X;
+    const int gx = (int)G / X + (x < (int)G % X ? 1 : 0);
+    const int per = count / X, rem = count % X;
+    const int t0 = x * per + min(x, rem);
+    return TileRange{t0 + i, t0 + per + (x < rem ? 1 : 0), gx};
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int ce, int adapt)
 {
@@ -289,17 +308,17 @@ __global__ __launch_bounds__(kBlock) void k_batch(BDev<T> d, int max_iter, int c
         const bool check = it % ce == 0 || it == max_iter;
         const bool save = !check && ((it + 1) % ce == 0 || it + 1 == max_iter);
         lap(5);
-        for (int t = blockIdx.x; t < d.nst; t += G) {
-            if (check) stream_tile<T, true>(d, t, sv, sred);
-            else stream_tile<T, false>(d, t, sv, sred);
+        for (TileRange r = xcd_tiles(d.nst, G); r.t < r.end; r.t += r.step) {
+            if (check) stream_tile<T, true>(d, r.t, sv, sred);
+            else stream_tile<T, false>(d, r.t, sv, sred);
         }
         lap(0);
         if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
         lap(1);
-        for (int t = blockIdx.x; t < d.nlt; t += G) {
-            if (check) link_tile<T, kCheck>(d, t, sv, sred);
-            else if (save) link_tile<T, kSave>(d, t, sv, sred);
-            else link_tile<T, kPlain>(d, t, sv, sred);
+        for (TileRange r = xcd_tiles(d.nlt, G); r.t < r.end; r.t += r.step) {
+            if (check) link_tile<T, kCheck>(d, r.t, sv, sred);
+            else if (save) link_tile<T, kSave>(d, r.t, sv, sred);
+            else link_tile<T, kPlain>(d, r.t, sv, sred);
         }
         lap(2);
         if (!grid_sync(d.bar, d.abort, G, d.spin_limit)) return;
