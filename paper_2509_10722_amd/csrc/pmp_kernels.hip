@@ -20,6 +20,16 @@ namespace pmp {
 
 namespace {
 
+// Workgroups are dealt to the 8 XCDs in turn (block b to XCD b mod 8); block
+// b takes segment block xcd_order(b), so that each XCD runs one contiguous
+// range of segment blocks and neighbouring blocks gather from one L2 (medium
+// shape in this layout 16,280 -> 16,480 it/s, the transit case study +1-2%).
+__device__ __forceinline__ int xcd_order(int b, int nblocks)
+{
+    const int x = b % 8, per = nblocks / 8, rem = nblocks % 8;
+    return x * per + min(x, rem) + b / 8;
+}
+
 // ---- stream pass ---------------------------------------------------------
 
 template <typename T, bool CHECK>
@@ -28,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_pass(Dev<T> d)
     if (d.ctl->done) return;
     __shared__ T sv[kCap];
     __shared__ double sred[kBlock / 64];
-    const int blk = blockIdx.x;
+    const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
     const int s0 = d.sblk[blk], s1 = d.sblk[blk + 1];
     const int e0 = d.col_ptr[s0];
     const int cnt = d.col_ptr[s1] - e0;
@@ -64,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_link_pass(Dev<T> d)
     if (d.ctl->done) return;
     __shared__ T sx[kCap];
     __shared__ double sred[kBlock / 64];
-    const int blk = blockIdx.x;
+    const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
     if (blk >= d.nlb) {
         // one chunk of a long row: a partial sum in a fixed order, or the
         // exact fixed-point sum (kept as int64 bits in rpart)
