@@ -652,7 +652,7 @@ namespace {
 
 struct AdjLayout {
     size_t ckpt, final_state, xK, tape_x, tape_mu, A, Sbar, wbar, ext, B, Z, U, ybar, cbar;
-    size_t my, ms;   // binned layout: FP64 messages of ybar and Sbar
+    size_t my, ms;   // binned layout: messages of ybar and Sbar (problem precision)
     size_t part, J, total, state;
     int nck, nobj;
 };
@@ -687,8 +687,10 @@ AdjLayout adj_plan(int m, int n, long long msgs, int K, int s, size_t sz)
     L.part = take((size_t)L.nobj * 8);
     L.J = take(8);
     if (msgs > 0) {
-        L.my = take((size_t)msgs * 8);
-        L.ms = take((size_t)msgs * 8);
+        // messages in the problem's precision, with the 4 slots of padding
+        // that the 4-wide FP32 loads of the accumulation may touch
+        L.my = take((size_t)(msgs + 4) * sz);
+        L.ms = take((size_t)(msgs + 4) * sz);
     }
     L.total = off;
     return L;
@@ -785,7 +787,7 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
     pmp_status rc;
     T *tape_x = (T *)(ws + L.tape_x);
     uint8_t *tape_mu = (uint8_t *)(ws + L.tape_mu);
-    double *my = (double *)(ws + L.my), *ms = (double *)(ws + L.ms);
+    T *my = (T *)(ws + L.my), *ms = (T *)(ws + L.ms);
     launch_ctl_clear_done(h->ctl, st);
     // adjoint seeds from x^K
     if (h->n) HIP_TRY(hipMemcpyAsync(d.x, ws + L.xK, (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));

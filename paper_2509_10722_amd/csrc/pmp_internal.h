@@ -252,15 +252,16 @@ template <typename T>
 void launch_bin_emit(const Dev<T> &d, int apply, hipStream_t s);
 void binned_configure();
 // Reverse mode in the binned layout: my holds ybar in the v-message layout,
-// ms holds Sbar in the x-message layout (FP64, one per nonzero each).
+// ms holds Sbar in the x-message layout (the problem's precision, one per
+// nonzero each, summed in FP64).
 template <typename T>
 void launch_bin_adj_stream(const Dev<T> &d, const AdjDev &a, const T *xt, int last,
-                           const double *my, double *ms, hipStream_t s);
+                           const T *my, T *ms, hipStream_t s);
 template <typename T>
 void launch_bin_adj_link(const Dev<T> &d, const AdjDev &a, const uint8_t *mu_prev,
-                         const double *ms, double *my, hipStream_t s);
+                         const T *ms, T *my, hipStream_t s);
 template <typename T>
-void launch_bin_adj_emit(const Dev<T> &d, const AdjDev &a, double *my, hipStream_t s);
+void launch_bin_adj_emit(const Dev<T> &d, const AdjDev &a, T *my, hipStream_t s);
 
 // Batched solve (pmp_batch.hip): many instances concatenated block-diagonally
 // into one global pattern, iterated together by one persistent kernel with
