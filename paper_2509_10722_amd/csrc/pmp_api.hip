@@ -798,12 +798,15 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
         if ((rc = copy_state<T>(h, ws + L.ckpt + (size_t)seg * L.state, false)) != PMP_OK) return rc;
         refresh_messages<T>(d, st);
         for (int t = t0 + 1; t <= t1; ++t) {            // recompute, recording x^t and mu^t
-            stream_pass<T>(d, kSave, st);               // kSave: x stored in both layouts
-            if (h->n)
-                HIP_TRY(hipMemcpyAsync(tape_x + (size_t)(t - t0 - 1) * h->n, d.x,
-                                       (size_t)h->n * sizeof(T), hipMemcpyDeviceToDevice, st));
+            // the passes of iteration t see the tape slot of x^t as their x:
+            // the stream pass writes x^t there (kSave: x stored in both
+            // layouts) and the gather layout's link pass reads it from there;
+            // the handle's own x is restored from x^K at the end
+            Dev<T> dt = d;
+            if (h->n) dt.x = tape_x + (size_t)(t - t0 - 1) * h->n;
+            stream_pass<T>(dt, kSave, st);
             launch_slack_mask<T>(d, tape_mu + (size_t)(t - t0 - 1) * h->m, st);
-            link_pass<T>(d, kPlain, 0, 0, st);
+            link_pass<T>(dt, kPlain, 0, 0, st);
         }
         if (t1 < K) {   // link step of iteration t1, deferred from the later segment
             launch_adj_link_only<T>(d, a, tape_mu + (size_t)(t1 - t0 - 1) * h->m, st);
