@@ -99,13 +99,6 @@ __global__ void k_adj_link_only(Dev<T> d, AdjDev a, const uint8_t *mu)
 }
 
 template <typename T>
-__global__ void k_slack_mask(Dev<T> d, uint8_t *mu)
-{
-    for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < d.m; l += gridDim.x * blockDim.x)
-        mu[l] = ((double)d.zs[l] - (double)d.u[l]) > -(double)d.c[l] ? 1 : 0;
-}
-
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_objective(Dev<T> d, double *part)
 {
     __shared__ double sred[kBlock / 64];
@@ -205,11 +198,6 @@ void launch_adj_link_only(const Dev<T> &d, const AdjDev &a, const uint8_t *mu, h
     hipLaunchKernelGGL((k_adj_link_only<T>), dim3(grid_of(d.m)), dim3(kBlock), 0, s, d, a, mu);
 }
 
-template <typename T>
-void launch_slack_mask(const Dev<T> &d, uint8_t *mu, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_slack_mask<T>), dim3(grid_of(d.m)), dim3(kBlock), 0, s, d, mu);
-}
 
 template <typename T>
 void launch_objective(const Dev<T> &d, double *part, int nblocks, double *out, hipStream_t s)
@@ -246,7 +234,6 @@ void launch_copy_weights(const Dev<T> &d, const T *w_new, hipStream_t s)
                                      hipStream_t);                                           \
     template void launch_adj_link_only<T>(const Dev<T> &, const AdjDev &, const uint8_t *,   \
                                           hipStream_t);                                      \
-    template void launch_slack_mask<T>(const Dev<T> &, uint8_t *, hipStream_t);              \
     template void launch_objective<T>(const Dev<T> &, double *, int, double *, hipStream_t); \
     template void launch_adj_init<T>(const Dev<T> &, const AdjDev &, hipStream_t);           \
     template void launch_adj_out<T>(const Dev<T> &, const AdjDev &, T *, T *, hipStream_t);  \

@@ -802,10 +802,11 @@ pmp_status backward_impl(pmp_handle *h, T *gc, T *gw)
             // the stream pass writes x^t there (kSave: x stored in both
             // layouts) and the gather layout's link pass reads it from there;
             // the handle's own x is restored from x^K at the end
+            // and the link pass records the slack mask mu^t in its tape slot
             Dev<T> dt = d;
             if (h->n) dt.x = tape_x + (size_t)(t - t0 - 1) * h->n;
+            dt.mu_out = tape_mu + (size_t)(t - t0 - 1) * h->m;
             stream_pass<T>(dt, kSave, st);
-            launch_slack_mask<T>(d, tape_mu + (size_t)(t - t0 - 1) * h->m, st);
             link_pass<T>(dt, kPlain, 0, 0, st);
         }
         if (t1 < K) {   // link step of iteration t1, deferred from the later segment

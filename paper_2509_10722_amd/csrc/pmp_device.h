@@ -197,6 +197,7 @@ __device__ __forceinline__ double link_update_in(const Dev<T> &d, int l, int deg
     const double c = in.c, u = in.u, b = in.b, zs = in.zs;
     const double al = d.alpha;
     const double ps = fmax(zs - u, -c);                 // slack prox
+    if (d.mu_out) d.mu_out[l] = zs - u > -c ? 1 : 0;    // its branch, for reverse mode
     const double cnt = (double)deg + 1.0;               // |l| = d_l + 1
     const double pbar = (y + ps) / cnt;                 // link average
     const T bt = (T)(-al * pbar + (1.0 - al) * b);

@@ -121,6 +121,9 @@ struct Dev {
     double fx_scale, fx_inv;        // 2^fx_shift, 2^-fx_shift
     Ctl *ctl;
     HistEntry *hist;
+    // When set (reverse mode's recomputation), the link pass also writes the
+    // slack-prox mask [zs - u > -c] of each link here.
+    uint8_t *mu_out;
     // Binned message layout (pmp_binned.hip); P link blocks of at most LB
     // links and Q stream blocks of at most SB streams tile R into P x Q tiles.
     int binned;                     // 1: iterations use the binned kernels
@@ -329,8 +332,6 @@ template <typename T>
 void launch_adj_link(const Dev<T> &d, const AdjDev &a, const uint8_t *mu_prev, hipStream_t s);
 template <typename T>
 void launch_adj_link_only(const Dev<T> &d, const AdjDev &a, const uint8_t *mu, hipStream_t s);
-template <typename T>
-void launch_slack_mask(const Dev<T> &d, uint8_t *mu, hipStream_t s);
 template <typename T>
 void launch_objective(const Dev<T> &d, double *part, int nblocks, double *out, hipStream_t s);
 template <typename T>
