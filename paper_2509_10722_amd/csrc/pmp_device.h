@@ -45,8 +45,9 @@ __device__ __forceinline__ long long fx_term(double x, double scale)
     return __double2ll_rn(x * scale);
 }
 
-// Exact int64 sum over a workgroup of kBlock threads (valid in thread 0);
-// `sh` holds kBlock / 64 doubles, reused as int64.
+// Exact int64 sum over a workgroup of NT threads (valid in thread 0); `sh`
+// holds NT / 64 doubles, reused as int64.
+template <int NT = kBlock>
 __device__ __forceinline__ long long block_sum_ll(long long v, double *sh)
 {
 #pragma unroll
@@ -57,23 +58,24 @@ __device__ __forceinline__ long long block_sum_ll(long long v, double *sh)
     __syncthreads();
     long long r = 0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < kBlock / 64; ++i) r += s[i];
+        for (int i = 0; i < NT / 64; ++i) r += s[i];
     __syncthreads();
     return r;
 }
 
-// Stage tab[idx[i]] for i < cnt into LDS.  Every lane first loads its share of
-// the index stream, then issues all of its gathers, then writes LDS, so up to
-// kCap / kBlock gathers per lane are in flight together.
-template <typename T>
+// Stage tab[idx[i]] for i < cnt into LDS with a workgroup of NT threads.
+// Every lane first loads its share of the index stream, then issues all of
+// its gathers, then writes LDS, so up to kCap / NT gathers per lane are in
+// flight together.
+template <typename T, int NT = kBlock>
 __device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
                                              const T *__restrict__ tab, T *sh, int cnt)
 {
-    constexpr int R = kCap / kBlock;
+    constexpr int R = kCap / NT;
     int id[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = r * kBlock + threadIdx.x;
+        const int i = r * NT + threadIdx.x;
         id[r] = i < cnt ? ld_stream(idx + i) : -1;
     }
     T val[R];
@@ -81,7 +83,7 @@ __device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
     for (int r = 0; r < R; ++r) val[r] = id[r] >= 0 ? tab[id[r]] : T(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = r * kBlock + threadIdx.x;
+        const int i = r * NT + threadIdx.x;
         if (i < cnt) sh[i] = val[r];
     }
 }
