@@ -297,7 +297,7 @@ pmp_status pmp_backward(pmp_handle *h, void *grad_c, void *grad_w);
  * graph-captured kernel launch per pmp_batch_solve: every instance keeps its
  * own rho, residuals, stop flag and iteration count (Section III-F/G applied
  * per instance), and stopped instances drop out of the work.  Workgroup tiles
- * never straddle instances; their nonzero limit (tile_cap, in [64, 4096]) is
+ * never straddle instances; their nonzero limit (tile_cap, in [64, 8192]) is
  * set per instance size class: m < class_m[0], m < class_m[1], larger.
  * With reorder_streams = 1 each instance's streams are renumbered inside the
  * library by the first link of their route (ties by index), which puts the
@@ -327,7 +327,7 @@ typedef struct {
 } pmp_batch_options;
 
 /* Defaults (tuned on MI355X for transit batches): classes at m = 1e4 and
- * 5e4, tile caps 4096 for every class, reorder_streams 1, wg_per_cu 4,
+ * 5e4, tile caps 8192 for every class, reorder_streams 1, wg_per_cu 4,
  * heavy_chunk 8192, wait_log2 24. */
 pmp_status pmp_batch_options_default(pmp_batch_options *options);
 pmp_status pmp_batch_workspace_size(int32_t count, const pmp_problem *problems,

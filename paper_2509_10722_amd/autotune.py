@@ -23,7 +23,7 @@ import json
 import os
 import time
 
-CANDIDATES = (512, 1024, 2048, 4096)
+CANDIDATES = (1024, 2048, 4096, 8192)
 GRID_CANDIDATES = (1, 2, 4, 8)          # resident workgroups per CU
 HEAVY_CANDIDATES = (1024, 2048, 4096, 8192, 16384, 65536)   # nonzeros per chunk of a long row
 CLASS_NAMES = ("small", "medium", "large")

@@ -38,6 +38,14 @@ constexpr int kWaitLog2Default = 24;
 // and columns are still summed by the first kBlock lanes in the stride of the
 // single-instance kernels, so their sums stay the same bit for bit.
 constexpr int kBT = 2 * kBlock;
+// Nonzeros a tile stages in LDS (the largest tile_cap): twice the passes'
+// kCap, for the twice as many lanes (16 gathers in flight per lane, as there).
+// Rows and columns longer than kCap still go their own way (chunk tiles,
+// strided sums), as in the single-instance kernels.  64-instance transit
+// solve: 1.35 s with 4096-nonzero tiles of at most 512 streams, 1.29 s with
+// 8192, 1.20 s with 8192 and 1,024 streams (2,048 streams: 1.21 s; 16384-
+// nonzero tiles: 1.80 s).
+constexpr int kBS = 2 * kCap;
 
 // Grid barrier in two levels.  Blocks are dealt to the 8 XCDs in turn, so
 // the blocks with one value of blockIdx.x mod 8 (one XCD) first meet on their
@@ -120,8 +128,8 @@ __device__ void stream_tile(const BDev<T> &d, int tile, T *sv, double *sred)
     const int cnt = di.col_ptr[s1] - e0;
     const double rho = d.ictl[inst].rho;
     double part = 0.0;
-    if (cnt <= kCap) {
-        gather_stage<T, kBT>(di.row_idx + e0, di.v, sv, cnt);
+    if (cnt <= kBS && !(s1 - s0 == 1 && cnt > kCap)) {
+        gather_stage<T, kBT, kBS>(di.row_idx + e0, di.v, sv, cnt);
         __syncthreads();
         for (int j = s0 + (int)threadIdx.x; j < s1; j += kBT) {
             const int b = di.col_ptr[j] - e0, e = di.col_ptr[j + 1] - e0;
@@ -227,7 +235,7 @@ __device__ void link_tile(const BDev<T> &d, int tile, T *sx, double *sred)
         const int l0 = d.lt_seg[tile], l1 = d.lt_seg[tile + 1];
         const int e0 = di.row_ptr[l0];
         const int cnt = di.row_ptr[l1] - e0;
-        gather_stage<T, kBT>(di.col_idx + e0, di.x, sx, cnt);
+        gather_stage<T, kBT, kBS>(di.col_idx + e0, di.x, sx, cnt);
         __syncthreads();
         const int l = l0 + (int)threadIdx.x;
         if (l < l1) {
@@ -294,7 +302,7 @@ __device__ __forceinline__ TileRange xcd_tiles(int count, unsigned G)
 template <typename T>
 __global__ __launch_bounds__(kBT) void k_batch(BDev<T> d, int max_iter, int ce, int adapt)
 {
-    __shared__ T sv[kCap];
+    __shared__ T sv[kBS];
     __shared__ double sred[kBT / 64];
     const unsigned G = gridDim.x;
     // phase clocks (profile only): thread 0 adds each phase's duration
@@ -527,11 +535,11 @@ bool sizes_of(int count, const pmp_problem *pr, BatchSizes &z)
     return z.M < (1LL << 31) && z.N < (1LL << 31) && z.NNZ < (1LL << 31);
 }
 
-// Streams per stream tile: two per lane.  Short routes (transit trips of 2-12
-// links) fill a 256-stream tile to only about 1,800 nonzeros; with two per
-// lane the tiles hold about twice that and the 64-instance transit solve
-// takes 1.41 s instead of 1.50 s (four per lane: 1.42 s).
-constexpr int kStreamSegs = 2 * kBlock;
+// Streams per stream tile: up to 1,024, two per lane of the 512.  Short
+// routes (transit trips of 2-12 links) fill a tile of 256 streams to only
+// about 1,800 nonzeros (with 256-lane workgroups and 4096-nonzero tiles, 512
+// streams per tile took the solve from 1.50 to 1.41 s).
+constexpr int kStreamSegs = 4 * kBlock;
 
 int heavy_chunk_of(const pmp_batch_options *o) { return o->heavy_chunk > 0 ? o->heavy_chunk : kLongChunk; }
 
@@ -565,7 +573,8 @@ void tiles_for(const std::vector<int> &ptr, int first, int last, int cap, int in
         if (ck) ck->push_back(make_int2(0, 0));
         int e = s;
         long long cnt = 0;
-        while (e < last && e - s < seg_cap && cnt + (ptr[e + 1] - ptr[e]) <= cap) {
+        while (e < last && e - s < seg_cap && ptr[e + 1] - ptr[e] <= kCap &&
+               cnt + (ptr[e + 1] - ptr[e]) <= cap) {
             cnt += ptr[e + 1] - ptr[e];
             ++e;
         }
@@ -917,9 +926,9 @@ pmp_status pmp_batch_options_default(pmp_batch_options *o)
     o->class_m[0] = 10000;
     o->class_m[1] = 50000;
     // the autotuner's choice on MI355X for the transit batch of Section VI
-    o->tile_cap[0] = 4096;
-    o->tile_cap[1] = 4096;
-    o->tile_cap[2] = 4096;
+    o->tile_cap[0] = kBS;
+    o->tile_cap[1] = kBS;
+    o->tile_cap[2] = kBS;
     o->reorder_streams = 1;
     o->wg_per_cu = 4;
     o->profile = 0;
@@ -933,8 +942,8 @@ static pmp_status check_batch_args(int32_t count, const pmp_problem *pr, const p
 {
     if (count < 1 || !pr || !prm || !opt) return set_error(PMP_ERR_INVALID, "bad batch arguments");
     for (int c = 0; c < 3; ++c)
-        if (opt->tile_cap[c] < 64 || opt->tile_cap[c] > kCap)
-            return set_error(PMP_ERR_INVALID, "tile_cap must be in [64, %d]", kCap);
+        if (opt->tile_cap[c] < 64 || opt->tile_cap[c] > kBS)
+            return set_error(PMP_ERR_INVALID, "tile_cap must be in [64, %d]", kBS);
     if (opt->wg_per_cu < 0 || opt->wg_per_cu > 8)
         return set_error(PMP_ERR_INVALID, "wg_per_cu must be in [0, 8]");
     if (opt->heavy_chunk != 0 && (opt->heavy_chunk < 1024 || opt->heavy_chunk > (1 << 20)))

@@ -67,11 +67,11 @@ __device__ __forceinline__ long long block_sum_ll(long long v, double *sh)
 // Every lane first loads its share of the index stream, then issues all of
 // its gathers, then writes LDS, so up to kCap / NT gathers per lane are in
 // flight together.
-template <typename T, int NT = kBlock>
+template <typename T, int NT = kBlock, int CAP = kCap>
 __device__ __forceinline__ void gather_stage(const int *__restrict__ idx,
                                              const T *__restrict__ tab, T *sh, int cnt)
 {
-    constexpr int R = kCap / NT;
+    constexpr int R = CAP / NT;
     int id[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -143,7 +143,7 @@ def test_batch_options_heavy_chunk_range(chunk, status):
     from paper_2509_10722_amd import pmp
     lib = pmp.load_library()
     o = pmp.batch_options_default()
-    assert (list(o.tile_cap), o.wg_per_cu, o.heavy_chunk) == ([4096] * 3, 4, 8192)
+    assert (list(o.tile_cap), o.wg_per_cu, o.heavy_chunk) == ([8192] * 3, 4, 8192)
     o.heavy_chunk = chunk
     prob = pmp.pmp_problem(m=10, n=20, nnz=50, dtype=pmp.PMP_F32)
     prm = pmp.params_default()

@@ -53,7 +53,7 @@ def test_batch_fp32_equal_iterations_vs_oracle():
 def test_tile_caps_do_not_change_iterates():
     insts = _small_batch(count=5)
     outs = []
-    for caps in ((64, 64, 64), (4096, 4096, 4096), (512, 1024, 2048)):
+    for caps in ((64, 64, 64), (8192, 8192, 8192), (512, 1024, 2048), (4096, 8192, 4096)):
         b = BatchSolver(insts, dtype=torch.float64, eps_abs=0.0,
                         options=batch_options_default(tile_cap=caps))
         b.solve(90)
