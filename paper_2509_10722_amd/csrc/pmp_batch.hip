@@ -63,6 +63,17 @@ constexpr int kBS = 2 * kCap;
 constexpr int kBarTop = 0, kBarGen = 64, kBarAbort = 128, kBarGroup = 192;
 constexpr int kBarWords = kBarGroup + 64 * 8;   // unsigned words of BDev::bar
 
+// Blocks of barrier group x (blockIdx.x mod 8 == x) in a grid of nblocks,
+// and the number of groups.
+__host__ __device__ __forceinline__ unsigned barrier_group_size(unsigned x, unsigned nblocks)
+{
+    return nblocks / 8 + (x < nblocks % 8 ? 1u : 0u);
+}
+__host__ __device__ __forceinline__ unsigned barrier_groups(unsigned nblocks)
+{
+    return nblocks < 8 ? nblocks : 8u;
+}
+
 __device__ bool grid_sync(unsigned *bar, int *abort, unsigned nblocks, unsigned long long spin_limit)
 {
     __shared__ int s_ok;
@@ -72,8 +83,8 @@ __device__ bool grid_sync(unsigned *bar, int *abort, unsigned nblocks, unsigned 
         unsigned *top = bar + kBarTop, *genp = bar + kBarGen;
         const unsigned x = blockIdx.x % 8;
         unsigned *grp = bar + kBarGroup + 64 * x;
-        const unsigned gsize = nblocks / 8 + (x < nblocks % 8 ? 1u : 0u);
-        const unsigned groups = nblocks < 8 ? nblocks : 8u;
+        const unsigned gsize = barrier_group_size(x, nblocks);
+        const unsigned groups = barrier_groups(nblocks);
         const unsigned gen = __hip_atomic_load(genp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         bool last = false;
@@ -289,14 +300,18 @@ __device__ __forceinline__ int find_instance(const int *off, int B, int idx)
 struct TileRange {
     int t, end, step;
 };
-__device__ __forceinline__ TileRange xcd_tiles(int count, unsigned G)
+__host__ __device__ __forceinline__ TileRange xcd_tiles_of(int count, unsigned G, unsigned b)
 {
-    const int X = (int)min(G, 8u);
-    const int x = (int)blockIdx.x % X, i = (int)blockIdx.x / X;
+    const int X = (int)(G < 8u ? G : 8u);
+    const int x = (int)b % X, i = (int)b / X;
     const int gx = (int)G / X + (x < (int)G % X ? 1 : 0);
     const int per = count / X, rem = count % X;
-    const int t0 = x * per + min(x, rem);
+    const int t0 = x * per + (x < rem ? x : rem);
     return TileRange{t0 + i, t0 + per + (x < rem ? 1 : 0), gx};
+}
+__device__ __forceinline__ TileRange xcd_tiles(int count, unsigned G)
+{
+    return xcd_tiles_of(count, G, blockIdx.x);
 }
 
 template <typename T>

@@ -241,6 +241,22 @@ int main()
         inf.hi = 10.0;
         REQUIRE(validate_host(inf, rep) == PMP_OK);
     }
+    // the batch kernel's index maps: each phase's tiles dealt to the grid
+    // exactly once, and the barrier groups adding up to the grid
+    for (unsigned G : {1u, 5u, 8u, 9u, 100u, 512u, 1000u, 1024u}) {
+        unsigned total = 0;
+        for (unsigned x = 0; x < barrier_groups(G); ++x) total += barrier_group_size(x, G);
+        REQUIRE(total == G);
+        for (int count : {0, 1, 7, 100, 10711, 24437}) {
+            std::vector<int> seen((size_t)count, 0);
+            for (unsigned b = 0; b < G; ++b)
+                for (TileRange r = xcd_tiles_of(count, G, b); r.t < r.end; r.t += r.step) {
+                    REQUIRE(r.t >= 0 && r.t < count);
+                    ++seen[(size_t)r.t];
+                }
+            for (int v : seen) REQUIRE(v == 1);
+        }
+    }
     std::printf("host planners: all checks passed\n");
     return 0;
 }
