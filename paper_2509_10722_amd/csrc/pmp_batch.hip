@@ -6,7 +6,8 @@
 // persistent kernel (grid sized to what the GPU holds at once) walks the
 // iterations: in each phase the workgroups of one XCD share a contiguous
 // eighth of the phase's tile list (xcd_tiles), skipping tiles of instances
-// that have stopped, and a grid barrier separates the phases.  Check iterations add a finalize phase
+// that have stopped, and a grid barrier separates the phases.  Check
+// iterations add a finalize phase
 // (workgroup i reduces instance i's tile partials in a fixed order and takes
 // its stop and rho decisions, Section III-F/G) and, at balancing iterations,
 // a rescale phase.  Tiles never straddle two instances; their size limit is
@@ -164,7 +165,8 @@ __device__ void stream_tile(const BDev<T> &d, int tile, T *sv, double *sred)
 }
 
 // Chunk k of the nch chunks of a long link row (a congested link): its sum
-// over heavy_chunk nonzeros (strided over the workgroup, then a fixed tree;
+// over heavy_chunk nonzeros (strided over the first kBlock lanes, then a
+// fixed tree;
 // in fixed point where the instance's long rows are), published in lt_hsum.
 // The workgroup that makes the row's last arrival adds the row's chunk sums
 // in chunk order and runs the link update; that order and these chunks are
@@ -565,7 +567,8 @@ int class_cap(const pmp_batch_options *o, int m)
 }
 
 // Greedy tiles over segments [first, last) of one instance: at most seg_cap
-// segments and `cap` nonzeros each (a longer segment alone).  With `ck`
+// segments and `cap` nonzeros each (a longer segment, or one of more than
+// kCap nonzeros, alone).  With `ck`
 // (link rows), a row longer than kCap becomes ceil(len / chunk) chunk tiles
 // that all start at that row.
 void tiles_for(const std::vector<int> &ptr, int first, int last, int cap, int inst,
