@@ -654,7 +654,7 @@ def main():
             k1 = args.cpu_single_iters
             r1 = oracle.run(inst32, k1, threads=1)
             cpu["single_thread"] = {"value": round(k1 / r1["loop_seconds"], 4), "unit": "iter/s",
-                                    "sample": f"{k1} iterations on one thread "
+                                    "sample": f"{k1} iteration{'s' if k1 != 1 else ''} on one thread "
                                               f"({r1['loop_seconds']:.1f} s)"}
         log(f"[bench] cpu baseline: {cpu}")
 
