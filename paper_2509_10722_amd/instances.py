@@ -343,6 +343,34 @@ def block_diagonal(parts):
                     np.concatenate([p.utility for p in parts]).astype(np.uint8), lo, hi)
 
 
+def edge_shapes(seed=11, m=6000, n=9000, hi=20.0):
+    """Ragged shapes for parity tests: stream 0 on a route of 5000 links
+    (longer than one workgroup's 4096-entry stage), the last link on 4500
+    streams, links m-10 .. m-2 on no stream, stream n-1 with an empty route
+    (its rate is then hi, so hi must be finite), and the rest on routes of
+    1-3 links; 30% linear utilities."""
+    rng = np.random.default_rng(seed)
+    link, stream = [], []
+    long_route = rng.choice(m - 10, 5000, replace=False)         # stream 0
+    link += list(long_route)
+    stream += [0] * 5000
+    busy = m - 1                                                  # link on 4500 streams
+    for j in range(1, 4501):
+        link.append(busy)
+        stream.append(j)
+    for j in range(1, n - 1):                                     # stream n-1: empty route
+        L = int(rng.integers(1, 4))
+        for l in rng.choice(m - 10, L, replace=False):
+            if not (j <= 4500 and l == busy):
+                link.append(int(l))
+                stream.append(j)
+    pairs = np.unique(np.array([link, stream]).T, axis=0)
+    row_ptr, col_idx = csr_from_pairs(m, n, pairs[:, 0], pairs[:, 1])
+    util = (rng.random(n) < 0.3).astype(np.uint8)
+    w = np.where(util == 0, rng.uniform(0.5, 2, n), rng.uniform(0.1, 1, n))
+    return Instance("edge", m, n, row_ptr, col_idx, rng.uniform(1, 50, m), w, util, 0.0, hi)
+
+
 def congested(base, link_frac=0.001, stream_frac=0.10, seed=6):
     """Section V-C's congestion: a random `link_frac` of the links is each
     added to the routes of a random `stream_frac` of the streams (pairs that

@@ -94,6 +94,42 @@ def test_batch_mixed_sizes_with_degenerate_instance():
     b.close()
 
 
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_batch_edge_shapes_match_plain_gather_solves(dtype_name):
+    """Ragged shapes inside a batch, next to an ordinary instance: a route of
+    5000 links (a stream tile of its own, summed strided) and a link on 4500
+    streams (a chunk tile), links no stream uses, a stream with an empty
+    route (its rate is hi) and single-link streams.  The iterates equal the
+    one-at-a-time gather solves bit for bit; in FP64 they also meet the
+    oracle at equal iteration count."""
+    dtype = getattr(torch, dtype_name)
+    insts = [I.edge_shapes(), I.tiny()]
+    if dtype_name == "float32":
+        insts = [i.rounded(np.float32) for i in insts]
+    K = 300
+    print(f"edge shapes in a batch, {dtype_name}, {K} iterations", flush=True)
+    b = BatchSolver(insts, dtype=dtype, eps_abs=0.0)
+    res = b.solve(K)
+    for k, inst in enumerate(insts):
+        s = Solver(inst, dtype=dtype, layout=1, eps_abs=0.0, max_iter=K)
+        r = s.solve()
+        x, lam, _ = s.solution()
+        xb, lb, _ = b.solution(k)
+        print(f"  instance {k} ({inst.name}): batch rho {res[k]['rho']}, plain rho {r['rho']}",
+              flush=True)
+        assert res[k]["iterations"] == r["iterations"] == K
+        assert res[k]["rho"] == r["rho"]
+        assert torch.equal(x, xb) and torch.equal(lam, lb)
+        s.close()
+    xe, le, _ = b.solution(0)
+    xe, le = host(xe), host(le)
+    assert xe[-1] == insts[0].hi
+    if dtype_name == "float64":
+        o = oracle.run(insts[0], K)
+        assert close(xe, o["x"], 64) and close(le, o["lam"], 64)
+    b.close()
+
+
 def test_stream_reordering_keeps_results():
     """Renumbering streams by their first link changes only where they live
     on the device, not any sum: results are identical and come back in the

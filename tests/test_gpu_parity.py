@@ -100,32 +100,8 @@ def test_medium_fp32_full_solve_equal_iterations():
     assert qx <= 1.0 and ql <= 1.0
 
 
-def _edge_instance():
-    """Ragged shapes: a route longer than one workgroup's LDS stage, a link
-    on more streams than that, links no stream uses, a stream with an empty
-    route (finite hi), single-link streams."""
-    rng = np.random.default_rng(11)
-    m, n = 6000, 9000
-    link, stream = [], []
-    long_route = rng.choice(m - 10, 5000, replace=False)         # stream 0
-    link += list(long_route); stream += [0] * 5000
-    busy = m - 1                                                  # link on 4500 streams
-    for j in range(1, 4501):
-        link.append(busy); stream.append(j)
-    for j in range(1, n - 1):                                     # stream n-1: empty route
-        L = int(rng.integers(1, 4))
-        for l in rng.choice(m - 10, L, replace=False):
-            if not (j <= 4500 and l == busy):
-                link.append(int(l)); stream.append(j)
-    pairs = np.unique(np.array([link, stream]).T, axis=0)
-    row_ptr, col_idx = I.csr_from_pairs(m, n, pairs[:, 0], pairs[:, 1])
-    util = (rng.random(n) < 0.3).astype(np.uint8)
-    w = np.where(util == 0, rng.uniform(0.5, 2, n), rng.uniform(0.1, 1, n))
-    return I.Instance("edge", m, n, row_ptr, col_idx, rng.uniform(1, 50, m), w, util, 0.0, 20.0)
-
-
 def test_edge_shapes_fp64():
-    inst = _edge_instance()
+    inst = I.edge_shapes()
     deg = np.diff(inst.row_ptr)
     assert deg.max() > 4096 and (deg == 0).sum() >= 5
     assert np.bincount(inst.col_idx, minlength=inst.n).max() > 4096

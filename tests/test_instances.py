@@ -118,3 +118,17 @@ def test_heavy_row_class_detection():
     assert not autotune.has_heavy_rows(base)
     assert autotune.has_heavy_rows(I.congested(base))
     assert not autotune.has_heavy_rows(I.congested(I.medium(scale=0.05)))   # rows of 2,500
+
+
+def test_edge_shapes_recipe():
+    """The ragged parity instance has what its docstring promises: a route
+    and a link longer than 4096 entries, unused links, an empty route."""
+    inst = I.edge_shapes()
+    _check_pattern(inst)
+    deg = np.diff(inst.row_ptr)
+    L = np.bincount(inst.col_idx, minlength=inst.n)
+    assert deg[inst.m - 1] == 4500 and deg.max() == 4500
+    assert np.all(deg[inst.m - 10:inst.m - 1] == 0)
+    assert L[0] == 5000 and L[inst.n - 1] == 0
+    assert L[1:inst.n - 1].min() >= 1 and L[1:inst.n - 1].max() <= 4
+    assert np.isfinite(inst.hi)
