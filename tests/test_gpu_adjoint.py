@@ -136,6 +136,63 @@ def test_envelope_tiny_reported():
     assert ec < 5e-2
 
 
+def test_adjoint_edge_shapes_fp64():
+    """Reverse mode on ragged shapes (a route of 5000 links and a link on
+    4500 streams, longer than one workgroup's stage; unused links; a stream
+    with an empty route), FP64, in both layouts.  Exact pins: the empty-route
+    stream's rate is hi whatever its weight, so dJ/dw there is U_j'(w) at
+    x = hi (log hi or hi), and a capacity no stream crosses cannot move any
+    rate, so dJ/dc is 0 there.  Then the two layouts against each other, and
+    the directional derivative against a central difference of the oracle
+    whose +h and -h runs took the prox branches of the unperturbed run in
+    every iteration (branch digest): with 9000 rates over 100 iterations a
+    step of 1e-6 already crosses a clip.  The oracle's J after 100 FP64
+    iterations moves by about 1e-13 |J| under rounding (the scatter of
+    kink-free differences between h = 5e-8 and 4e-7), so a difference at step
+    h carries about 1e-13 |J| / h; the gate is 4x that plus 1e-6 relative."""
+    inst = I.edge_shapes()
+    K, s = 100, 25
+    grads = {}
+    for layout, name in ((1, "gather"), (2, "binned")):
+        print(f"edge shapes: forward_ckpt({K}, {s}) + backward, FP64 {name}", flush=True)
+        solver = Solver(inst, dtype=torch.float64, adapt_every=0, layout=layout)
+        assert solver.layout_in_use() == name
+        solver.forward_ckpt(K, s)
+        gc, gw = solver.backward()
+        solver.close()
+        grads[name] = (host(gc), host(gw))
+    gc, gw = grads["gather"]
+    j = inst.n - 1
+    assert gw[j] == (np.log(inst.hi) if inst.utility[j] == 0 else inst.hi)
+    unused = np.flatnonzero(np.diff(inst.row_ptr) == 0)
+    assert unused.size >= 5 and np.all(gc[unused] == 0.0)
+    for k in range(2):
+        assert rel(grads["binned"][k], grads["gather"][k]) <= 1e-10
+    rng = np.random.default_rng(5)
+    dc = rng.normal(size=inst.m)
+    dw = rng.normal(size=inst.n)
+
+    def J_at(t):
+        p = I.Instance(inst.name, inst.m, inst.n, inst.row_ptr, inst.col_idx,
+                       inst.c + t * dc, inst.w + t * dw, inst.utility, inst.lo, inst.hi)
+        o = oracle.run(p, K, adapt_every=0, branches=True)
+        return _utility_sum(p, o["x"]), o["branch_digest"]
+
+    J0, d0 = J_at(0.0)
+    for h in (4e-7, 2e-7, 1e-7):
+        (jp, dp), (jm, dm) = J_at(h), J_at(-h)
+        if dp == d0 and dm == d0:
+            break
+    else:
+        pytest.fail("every step crossed a prox kink")
+    fd = (jp - jm) / (2 * h)
+    tol = 1e-6 * abs(fd) + 4.0 * 1e-13 * abs(J0) / h
+    an = float(gc @ dc + gw @ dw)
+    print(f"  directional derivative: adjoint {an:.10g}, central FD (h={h:g}) {fd:.10g}, "
+          f"|diff| / tol {abs(an - fd) / tol:.3f}", flush=True)
+    assert abs(an - fd) <= tol
+
+
 def test_autograd_function_fp32():
     inst = I.tiny().rounded(np.float32)
     solver = Solver(inst, dtype=torch.float32, adapt_every=0)
